@@ -1,0 +1,179 @@
+/* links.h -- C ABI of liblinks.so: batched kinematic simulation of one-degree-of-
+ * freedom planar linkages on AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow the LINKS paper (Nobari, Srivastava, Gutfreund, Ahmed,
+ * arXiv 2208.14567):
+ *   - a mechanism is an undirected graph given by its adjacency matrix plus, per
+ *     joint, a type (fixed, free, actuated) and an initial position; link lengths
+ *     are the initial distances (Methodology, "Mechanism Representation");
+ *   - the actuator arm joins a fixed pivot and an actuated tip, joints 0 and 1 in
+ *     the paper's dataset (Methodology, "Dataset Features & Statistics", item 1);
+ *   - the graphical solver finds, once per mechanism, the order in which joints
+ *     with two known neighbours can be placed (Methodology, "Graphical
+ *     Simulator");
+ *   - a mechanism is valid when the actuator completes a full rotation, sampled
+ *     at T equally spaced positions (200 in the dataset, 50 in the low-fidelity
+ *     pass), without locking (Methodology, "Finding Valid Initial Positions",
+ *     "Scale of Infeasibilities", "Dataset Features & Statistics" item 2);
+ *   - paths are normalised for comparison (Methodology, "Dataset Curation &
+ *     Processing").
+ *
+ * General conventions
+ *   - Every entry point returns LINKS_OK (0) or a negative error code; the text
+ *     of the last error on the calling thread is in links_last_error().
+ *   - Problems of a single candidate never fail a call: they are reported in its
+ *     status entry.
+ *   - All array pointers are DEVICE pointers (hipMalloc'd or equivalent) owned by
+ *     the caller; the library never keeps them after the call returns and never
+ *     frees them.  Calls are asynchronous on `stream` (a hipStream_t passed as
+ *     void*, NULL = the null stream); outputs are valid once the stream has
+ *     completed, and inputs must stay alive until then.
+ *   - A context owns device workspace that grows on demand; one context must not
+ *     be used by two threads at the same time.  Calls that overlap on one context
+ *     through different streams are not supported.
+ */
+#ifndef LINKS_H
+#define LINKS_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---- */
+#define LINKS_OK 0
+#define LINKS_ERR_ARG (-1)    /* null pointer, size out of range, bad option */
+#define LINKS_ERR_DEVICE (-2) /* a HIP runtime call failed */
+#define LINKS_ERR_OOM (-3)    /* workspace allocation failed */
+
+/* ---- per-candidate status ---- */
+#define LINKS_VALID 0       /* full rotation without locking */
+#define LINKS_LOCKED 1      /* two parent circles do not meet at some step */
+#define LINKS_DEGENERATE 2  /* the two parents coincide (d^2 <= 1e-12 scale^2) */
+#define LINKS_DRIFT 3       /* a redundant link changed length by > tau*scale */
+#define LINKS_UNSOLVABLE 4  /* the graphical solver cannot place every joint */
+#define LINKS_BAD_MECH 5    /* malformed input (see links_solve_order) */
+
+/* ---- precisions for links_simulate ---- */
+#define LINKS_FP32_RECHECK 0 /* FP32 with escalation to FP64 (default) */
+#define LINKS_FP64 1         /* plain FP64 throughout */
+#define LINKS_FP32_ONLY 2    /* FP32 without escalation (diagnostic) */
+
+/* ---- path output modes ---- */
+#define LINKS_WRITE_NONE 0
+#define LINKS_WRITE_ALL 1   /* path[B][T][2]; NaN from fail_step on */
+#define LINKS_WRITE_VALID 2 /* compacted: path[cap][T][2] + path_index[cap] */
+
+/* ---- path element types ---- */
+#define LINKS_F32 0
+#define LINKS_F64 1
+
+/* ---- normalisation ---- */
+#define LINKS_NORM_PCA 0      /* centroid, RMS radius 1, principal axis on +x */
+#define LINKS_NORM_DIAMETER 1 /* longest chord on +x, length 1, box centred at (0.5, 0.5) */
+#define LINKS_NF_CONSTANT 1   /* all points coincide: output zeros */
+#define LINKS_NF_ISOTROPIC 2  /* principal axis undefined (circle-like): no rotation */
+#define LINKS_NF_SIGN_TIE 4   /* third moment ~ 0: axis sign kept as found */
+#define LINKS_NF_DIAM_TIE 8   /* another chord within 1e-6 of the longest */
+
+typedef struct links_ctx links_ctx;
+
+/* Creates a context bound to HIP device `device` (the device is made current for
+ * the calls of this context).  *out receives the context. */
+int links_create(int device, links_ctx** out);
+void links_destroy(links_ctx* ctx);
+
+/* Message of the last failing call on this thread ("" if none).  The pointer is
+ * valid until the next call on the same thread. */
+const char* links_last_error(void);
+
+/* Version string of the library (static storage). */
+const char* links_version(void);
+
+/* A batch of B candidates with a per-candidate joint stride J (1 <= J <= 32).
+ * Layout of the representation in the paper's Methodology, "Mechanism
+ * Representation": adjacency matrix rows as bitmasks, a fixed-joint mask in
+ * place of type 0, the motor pair in place of the actuated type, and x0.
+ *   n     uint8  [B]       joint count, 3 <= n <= J
+ *   adj   uint32 [B][J]    bit j of adj[c][i] set iff joints i and j are linked
+ *   fixed uint32 [B]       bit i set iff joint i is a ground (fixed) joint
+ *   motor uint8  [B][2]    (pivot, tip): pivot fixed, tip free, link pivot-tip present
+ *   x0    double [B][J][2] initial positions; entries beyond n are ignored       */
+typedef struct {
+  int32_t B, J;
+  const uint8_t* n;
+  const uint32_t* adj;
+  const uint32_t* fixed;
+  const uint8_t* motor;
+  const double* x0;
+} links_batch;
+
+/* Graphical solve order (Methodology, "Graphical Simulator"): starting from the
+ * fixed joints and the tip, each round places, in ascending joint index, every
+ * unknown joint with at least two known neighbours, using the two smallest known
+ * neighbours as parents.
+ * Outputs (device, [B] unless stated):
+ *   order   int8 [B][J][3]  (joint, parent a, parent b) per placed joint, -1 padded
+ *   n_dyads placed joints; depth = number of rounds
+ *   status  LINKS_VALID (all joints placed), LINKS_UNSOLVABLE, or LINKS_BAD_MECH
+ *           when n is outside [3, J], adj is not symmetric, has a diagonal bit or
+ *           a bit at or beyond n, fixed has a bit at or beyond n, or the motor
+ *           pair is not (fixed pivot, free tip) joined by a link.
+ * Any output pointer except status may be NULL. */
+int links_solve_order(links_ctx* ctx, const links_batch* batch, int8_t* order, uint8_t* n_dyads,
+                      uint8_t* depth, uint8_t* status, void* stream);
+
+typedef struct {
+  int32_t T;           /* actuator positions per revolution, theta_t = 2 pi t / T, 1..32767 */
+  int32_t precision;   /* LINKS_FP32_RECHECK | LINKS_FP64 | LINKS_FP32_ONLY */
+  double eps_disc;     /* escalation band on disc = K/(4 scale^2), in units of scale^2 (1e-6) */
+  double eps_branch;   /* escalation band on the branch distance, in units of scale (1e-5) */
+  double tau_drift;    /* redundant-link drift limit, in units of scale (1e-4) */
+  int32_t out_joint;   /* joint whose path is written; -1 = last joint of the solve order */
+  int32_t write;       /* LINKS_WRITE_NONE | LINKS_WRITE_ALL | LINKS_WRITE_VALID */
+  int32_t path_dtype;  /* LINKS_F32 | LINKS_F64 */
+} links_sim_opts;
+
+/* Fills opts with the defaults above (T = 200, WRITE_NONE, F32). */
+void links_sim_opts_default(links_sim_opts* opts);
+
+typedef struct {
+  uint8_t* status;     /* [B] required */
+  int16_t* fail_step;  /* [B] nullable; step of the first failure, -1 if none */
+  int16_t* esc_step;   /* [B] nullable; step at which FP32 handed over to FP64, -1 if never */
+  void* path;          /* see write mode; element type path_dtype */
+  int32_t* path_index; /* WRITE_VALID: [cap] candidate index of each written path, ascending */
+  int32_t* n_written;  /* WRITE_VALID: [1] number of valid candidates (may exceed cap) */
+  int32_t cap;         /* WRITE_VALID: rows available in path / path_index */
+} links_sim_out;
+
+/* Full-rotation simulation of every candidate.  Per step t the tip is turned by
+ * theta_t about the pivot, fixed joints stay at x0, and every joint of the solve
+ * order is placed at an intersection of the circles about its two parents (radii
+ * = initial link lengths).  Of the two intersections the one nearer the joint's
+ * previous position is taken (the initial position at t = 0).  A candidate fails
+ * at the first step where two circles miss (LOCKED), its parents coincide
+ * (DEGENERATE) or a link outside the solve order drifts (DRIFT); decisions are
+ * taken in step order, then solve order.  Link lengths must exceed 1e-12 and
+ * positions must be finite, else BAD_MECH.
+ * FP32_RECHECK runs FP32 and hands a candidate over to the FP64 arithmetic at the
+ * first step where a decision lies within eps (or within the tracked FP32 error
+ * bound) of its threshold; FP64 results are identical to a correctly rounded
+ * double evaluation of the same formulas. */
+int links_simulate(links_ctx* ctx, const links_batch* batch, const links_sim_opts* opts,
+                   links_sim_out* out, void* stream);
+
+/* Path normalisation (Methodology, "Dataset Curation & Processing"), FP32.
+ *   paths [P][T][2] in, out [P][T][2], xform [P][5] = (cx, cy, s, phi, flags) with
+ *   out = R(-phi) (p - c) / s, plus (0.5, 0.5) in DIAMETER mode.
+ * PCA: c = centroid, s = RMS radius, phi = principal axis angle turned so that the
+ *   third moment along +x is positive.  DIAMETER: the paper's rule -- the longest
+ *   chord is turned to +x and scaled to length 1, and the bounding box is centred
+ *   at (0.5, 0.5).  out may alias paths. */
+int links_normalize_paths(links_ctx* ctx, const float* paths, int32_t P, int32_t T, int32_t mode,
+                          float* out, float* xform, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,70 @@
+/* links_ref.h -- FP64 CPU oracle for batched 1-DOF planar linkage simulation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, plain reference that the
+ * HIP path is checked against.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load it; the product path never does.
+ *
+ * All pointers are host pointers owned by the caller.  Layouts match the product
+ * library's inputs (row bitmask adjacency, fixed-joint mask, motor pair, x0).
+ * Return value: 0 on success, -1 on a bad argument (null pointer, J outside
+ * [1,32], T < 1, B < 0).  Per-candidate problems go to `status`.
+ */
+#ifndef LINKS_REF_H
+#define LINKS_REF_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* per-candidate status codes */
+#define LREF_VALID 0
+#define LREF_LOCKED 1
+#define LREF_DEGENERATE 2
+#define LREF_DRIFT 3
+#define LREF_UNSOLVABLE 4
+#define LREF_BAD_MECH 5
+
+/* normalisation modes and flags */
+#define LREF_NORM_PCA 0
+#define LREF_NORM_DIAMETER 1
+#define LREF_NF_CONSTANT 1
+#define LREF_NF_ISOTROPIC 2
+#define LREF_NF_SIGN_TIE 4
+#define LREF_NF_DIAM_TIE 8
+
+/* Graphical solve order (Methodology, "Graphical Simulator"): rounds of joints
+ * with two known neighbours.  order: [B][J][3] int8 (joint, parent a, parent b),
+ * -1 padded; n_dyads, depth, status: [B]. */
+int links_ref_solve_order(int32_t B, int32_t J, const uint8_t* n, const uint32_t* adj,
+                          const uint32_t* fixed, const uint8_t* motor, int8_t* order,
+                          uint8_t* n_dyads, uint8_t* depth, uint8_t* status);
+
+/* Full-rotation simulation in FP64.
+ * x0: [B][J][2].  T steps, crank angle 2*pi*t/T.  out_joint -1 = last solved joint.
+ * tau_drift: a redundant link whose length moves by more than tau_drift*scale
+ *   (scale = longest link) fails the candidate.
+ * status [B], fail_step [B] (-1 when valid or never simulated).
+ * path (nullable): [B][T][2] output joint positions, NaN from fail_step on.
+ * pos_all (nullable): [B][T][J][2] every joint, NaN from fail_step on.
+ * margins (nullable): [B][4] = min |disc|/scale^2 with disc = K/(4 scale^2) and
+ *   K = ((ra+rb)^2 - d^2)(d^2 - (ra-rb)^2) the intersection discriminant, min d^2/scale^2,
+ *   min branch distance/scale, min |drift - tau*scale|/scale over evaluated steps
+ *   (+inf where nothing was evaluated).
+ * nthreads: host threads over candidates (<=0: 1). */
+int links_ref_simulate(int32_t B, int32_t J, const uint8_t* n, const uint32_t* adj,
+                       const uint32_t* fixed, const uint8_t* motor, const double* x0,
+                       int32_t T, int32_t out_joint, double tau_drift, uint8_t* status,
+                       int16_t* fail_step, double* path,
+                       double* pos_all, double* margins, int32_t nthreads);
+
+/* Path normalisation in FP64.  paths, out: [P][T][2]; xform: [P][5] =
+ * (cx, cy, s, phi, flags) such that out = R(-phi)(p - c)/s, plus (0.5, 0.5) in
+ * DIAMETER mode. */
+int links_ref_normalize_paths(const double* paths, int32_t P, int32_t T, int32_t mode,
+                              double* out, double* xform);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,68 @@
+"""Seeded input generator: counter-based RNG and dyad-built topologies."""
+import numpy as np
+import pytest
+
+from paper_2208_14567_amd import gen
+
+
+def test_splitmix64_reference_outputs():
+    # first outputs of SplitMix64 seeded with 0 (Steele, Lea, Flood 2014 reference generator)
+    out = gen.draw_u64(np.uint64(0), np.arange(3))
+    assert [int(x) for x in out] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_counter_based_and_fp32_exact():
+    b1 = gen.workload("dyad_6_20", 1000, seed=5)
+    b2 = gen.workload("dyad_6_20", 600, seed=5, first=400)
+    assert np.array_equal(b1.adj[400:], b2.adj) and np.array_equal(b1.x0[400:], b2.x0)
+    # every coordinate is a multiple of 2^-24 in [0, 1): exact in FP32
+    x = b1.x0.ravel()
+    assert np.all(x.astype(np.float32).astype(np.float64) == x)
+    assert np.all((x * 2 ** 24) == np.floor(x * 2 ** 24)) and x.min() >= 0 and x.max() < 1
+
+
+def _mobility(b):
+    """Mobility m = 3(N-1) - 2 j1 of the paper's Eq. 1 with every edge a binary link
+    plus one ground body; a joint joining k bodies contributes k-1 pin pairs."""
+    m = np.zeros(b.B, np.int64)
+    for c in range(b.B):
+        n = int(b.n[c])
+        E = sum(bin(int(b.adj[c, i]) & ((1 << n) - 1)).count("1") for i in range(n)) // 2
+        bodies = E + 1
+        j1 = 0
+        for i in range(n):
+            k = bin(int(b.adj[c, i])).count("1") + ((int(b.fixed[c]) >> i) & 1)
+            j1 += max(k - 1, 0)
+        m[c] = 3 * (bodies - 1) - 2 * j1
+    return m
+
+
+@pytest.mark.parametrize("name", ["dyad_6_20", "dyad_skewed", "dyad_4_20", "paper_8_20"])
+def test_dyad_topologies_have_mobility_one(name):
+    b = gen.workload(name, 400, seed=9)
+    assert np.all(_mobility(b) == 1)
+    # symmetric, no self links, nothing beyond n
+    for c in range(b.B):
+        n = int(b.n[c])
+        A = np.array([[(int(b.adj[c, i]) >> j) & 1 for j in range(b.J)] for i in range(b.J)])
+        assert np.array_equal(A, A.T) and A.trace() == 0 and A[n:].sum() == 0
+        assert (int(b.fixed[c]) >> 0) & 1 and not (int(b.fixed[c]) >> 1) & 1 and A[0, 1] == 1
+
+
+def test_joint_count_distributions():
+    b = gen.workload("dyad_6_20", 60000, seed=2)
+    counts = np.bincount(b.n, minlength=21)[6:21]
+    assert counts.min() > 0.9 * 60000 / 15 and counts.max() < 1.1 * 60000 / 15
+    s = gen.workload("dyad_skewed", 60000, seed=3)
+    frac = [np.mean((s.n >= lo) & (s.n <= hi)) for lo, hi in ((6, 8), (9, 14), (15, 20))]
+    assert abs(frac[0] - 0.6) < 0.01 and abs(frac[1] - 0.3) < 0.01 and abs(frac[2] - 0.1) < 0.01
+
+
+def test_fourbar_rejection_gives_grashof_crank_rockers():
+    b = gen.workload("fourbar", 2000)
+    p = b.x0
+    L = lambda i, j: np.hypot(*(p[:, i] - p[:, j]).T)
+    crank, coupler, rocker, ground = L(0, 1), L(1, 3), L(2, 3), L(0, 2)
+    allL = np.stack([crank, coupler, rocker, ground], 1)
+    s, l = allL.min(1), allL.max(1)
+    assert np.all(crank == s) and np.all(s + l < allL.sum(1) - s - l)
