@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched linkage simulation on one MI355X.
+
+One step = the whole hot path over one resident batch of 1,000,000 synthetic
+dyad-built candidates (n ~ U{6..20}, x0 ~ U[0,1)^2, T = 200 actuator positions):
+validation and solve order, bucket sort by solve-order length, the FP32 pass,
+the FP64 hand-over pass, the FP64 path pass, compaction of the valid candidates'
+coupler paths and their PCA normalisation.  Inputs are in HBM before the timed
+region starts.
+
+Printed: one JSON line with the headline throughput (candidates decided per
+second, FP32 with FP64 escalation), the plain FP64 path on the same GPU, the
+roofline of the FP32 pass (HIP events around it on its stream) and the FP64 CPU
+oracle on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "mechanism sims/sec (200 steps) FP32+recheck vs FP64 plain; p99 request latency"
+
+# algorithmic floating-point operations, counted from the formulas (add, mul,
+# compare, min/max, sqrt/rsq/div = 1; fma = 2)
+FLOP_DYAD_FP32 = 40   # one placement: d^2, discriminant, 1/d, sqrt K, foot, normal, branch, lock/band tests
+FLOP_TIP = 8          # crank rotation of the tip per step
+FLOP_DYAD_FP64 = 42   # the FP64 step formula (two sqrt, four divisions, both branch distances)
+FP32_PEAK = 157.3e12
+FP64_PEAK = 78.6e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def executed_work(status, fail, esc, nd, T):
+    """FP32-pass steps fully completed per candidate and the dyad-steps they hold."""
+    steps = np.where(esc >= 0, esc, np.where(status == 0, T, np.where(fail >= 0, fail, 0))).astype(np.int64)
+    fp32_only = (esc < 0) & (status <= 3)
+    steps = np.where((esc >= 0) | fp32_only, steps, 0)
+    return steps, steps * nd.astype(np.int64)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--B", type=int, default=1_000_000)
+    ap.add_argument("--T", type=int, default=200)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2208_14567_amd import gen, links as L
+
+    dev = torch.device("cuda:0")
+    B, T = args.B, args.T
+    t0 = time.time()
+    host = gen.workload("dyad_6_20", B, seed=2)
+    log(f"generated {B} candidates in {time.time() - t0:.1f}s")
+    db = L.to_device(host, dev)
+    ctx = L.Context(0)
+    out = {"status": torch.empty(B, dtype=torch.uint8, device=dev),
+           "fail_step": torch.empty(B, dtype=torch.int16, device=dev),
+           "esc_step": torch.empty(B, dtype=torch.int16, device=dev),
+           "path": torch.empty((B, T, 2), dtype=torch.float32, device=dev),
+           "path_index": torch.empty(B, dtype=torch.int32, device=dev),
+           "n_written": torch.empty(1, dtype=torch.int32, device=dev)}
+    norm_out = torch.empty((B, T, 2), dtype=torch.float32, device=dev)
+    norm_xf = torch.empty((B, 5), dtype=torch.float32, device=dev)
+
+    def step(precision):
+        ctx.simulate(db, T=T, precision=precision, write=L.WRITE_VALID, cap=B, out=out)
+        ctx.normalize_paths_n(out["path"], out["n_written"], L.NORM_PCA, out=norm_out, xform=norm_xf)
+
+    def run(precision, label):
+        for _ in range(args.warmup):
+            step(precision)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        passes = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(precision)
+            passes.append(ctx.last_timings())
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ctx.profile(False)
+        mean = {k: float(np.mean([p[k] for p in passes])) for k in passes[0]}
+        log(f"{label}: {dt / args.steps * 1e3:.3f} ms/step, passes (ms): " +
+            ", ".join(f"{k} {v:.3f}" for k, v in mean.items()))
+        return dt / args.steps, mean
+
+    sec32, pass32 = run(L.FP32_RECHECK, "fp32+fp64-escalation")
+    st = out["status"].cpu().numpy()
+    fs = out["fail_step"].cpu().numpy()
+    es = out["esc_step"].cpu().numpy()
+    nw = int(out["n_written"].cpu()[0])
+    nd = ctx.solve_order(db)[1].cpu().numpy()
+    steps32, dsteps32 = executed_work(st, fs, es, nd, T)
+    flop32 = float(dsteps32.sum()) * FLOP_DYAD_FP32 + float(steps32.sum()) * FLOP_TIP
+    t32 = pass32["fp32_pass"] * 1e-3
+    achieved = flop32 / t32
+    decided = np.where(st == 0, T, fs.astype(np.int64) + 1)
+    stats = {
+        "valid_fraction": float((st == 0).mean()),
+        "escalated_fraction": float((es >= 0).mean()),
+        "valid_paths_written": nw,
+        "candidate_steps_per_s": float(decided.sum()) / sec32,
+        "dyad_steps_per_s": float((decided * nd).sum()) / sec32,
+        "fp32_pass_ms": pass32["fp32_pass"],
+        "fp64_pass_ms": pass32["fp64_pass"],
+        "fp64_path_pass_ms": pass32["fp64_path_pass"],
+        "passes_ms": pass32,
+    }
+
+    fp64 = None
+    if not args.no_fp64:
+        sec64, pass64 = run(L.FP64, "fp64 plain")
+        st64 = out["status"].cpu().numpy()
+        fs64 = out["fail_step"].cpu().numpy()
+        d64 = np.where(st64 == 0, T, np.where(fs64 >= 0, fs64, 0)).astype(np.int64)
+        flop64 = float((d64 * nd).sum()) * FLOP_DYAD_FP64 + float(d64.sum()) * FLOP_TIP
+        fp64 = {"value": B / sec64, "ms_per_step": sec64 * 1e3, "speedup_fp32_recheck_over_fp64": sec64 / sec32,
+                "fp64_pass_ms": pass64["fp64_pass"],
+                "roofline": {"bound": "alu", "achieved": flop64 / (pass64["fp64_pass"] * 1e-3) / 1e12,
+                             "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
+                             "frac": flop64 / (pass64["fp64_pass"] * 1e-3) / FP64_PEAK},
+                "status_equal_to_fp32_recheck_outside_escalation": None}
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        threads = os.cpu_count() or 1
+        threads = min(threads, 64)
+        n_s = 20000
+        while True:
+            sub = host.slice(0, min(n_s, B))
+            t0 = time.perf_counter()
+            oracle.simulate(sub, T=T, nthreads=threads)
+            wall = time.perf_counter() - t0
+            if wall * threads >= 10.0 or n_s >= B or wall > 20:
+                break
+            n_s = min(B, int(n_s * max(2.0, 12.0 / max(wall * threads, 1e-3))))
+        cpu = {"value": sub.B / wall, "unit": "sims/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {sub.B} candidates of the same batch, FP64, {threads} host threads, "
+                         f"{wall:.2f} s wall ({cpu_model()})"}
+        log(f"cpu oracle: {cpu['value']:.0f} sims/s on {threads} threads")
+
+    res = {
+        "metric": METRIC,
+        "value": B / sec32,
+        "unit": "sims/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec32 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "dyad_6_20: 1M dyad-built 1-DOF candidates, n~U{6..20}, x0~U[0,1)^2, T=200; "
+                               "FP32 with FP64 escalation; valid coupler paths compacted and PCA-normalised",
+                   "candidates": B, "T": T, "seed": 2},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_PEAK, "traffic": None, "kernel": "sim32_kernel (FP32 pass)",
+                     "flop_per_dyad_step": FLOP_DYAD_FP32, "dyad_steps": int(dsteps32.sum())},
+        "cpu_baseline": cpu,
+        "fp64_plain": fp64,
+        "stats": stats,
+    }
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

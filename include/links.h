@@ -163,6 +163,15 @@ typedef struct {
 int links_simulate(links_ctx* ctx, const links_batch* batch, const links_sim_opts* opts,
                    links_sim_out* out, void* stream);
 
+/* Launch parameters of the simulation passes (chosen by the autotuner in the
+ * Python layer, or set by hand): waves32 / waves64 = wavefronts per workgroup of
+ * the FP32 / FP64 pass (1..4); refill_min = idle lanes a wave waits for before it
+ * fetches new candidates (1..64).  Returns LINKS_ERR_ARG outside these ranges. */
+int links_set_tuning(links_ctx* ctx, int waves32, int refill_min, int waves64);
+/* Current launch parameters and the persistent grid sizes of the last call (any
+ * pointer may be NULL). */
+int links_get_tuning(links_ctx* ctx, int* waves32, int* refill_min, int* waves64, int* grid32, int* grid64);
+
 /* Path normalisation (Methodology, "Dataset Curation & Processing"), FP32.
  *   paths [P][T][2] in, out [P][T][2], xform [P][5] = (cx, cy, s, phi, flags) with
  *   out = R(-phi) (p - c) / s, plus (0.5, 0.5) in DIAMETER mode.
@@ -172,6 +181,22 @@ int links_simulate(links_ctx* ctx, const links_batch* batch, const links_sim_opt
  *   at (0.5, 0.5).  out may alias paths. */
 int links_normalize_paths(links_ctx* ctx, const float* paths, int32_t P, int32_t T, int32_t mode,
                           float* out, float* xform, void* stream);
+
+/* Same as links_normalize_paths for the first min(*count, cap) rows, where count
+ * is a DEVICE int32 (for instance n_written of a WRITE_VALID simulation), so a
+ * simulate -> normalise pipeline needs no host synchronisation. */
+int links_normalize_paths_n(links_ctx* ctx, const float* paths, const int32_t* count, int32_t cap, int32_t T,
+                            int32_t mode, float* out, float* xform, void* stream);
+
+/* Kernel timing.  With profiling enabled the next links_simulate records HIP
+ * events around each of its passes on the call's stream; links_last_timings
+ * synchronises with the last recorded event and writes the elapsed milliseconds
+ * of up to n passes, in this order: prep, bucket sort, FP32 pass, FP64 hand-over
+ * pass (or the FP64 pass in FP64 precision), FP64 path pass, compaction.  A pass
+ * that did not run reports 0.  Returns the number of values written. */
+#define LINKS_TIMING_PASSES 6
+int links_profile(links_ctx* ctx, int enable);
+int links_last_timings(links_ctx* ctx, float* ms, int n);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,481 @@
+// api.cpp -- host runtime behind the C ABI of include/links.h: argument checks,
+// workspace management, the crank table and the launch sequence of one call.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/links.h"
+#include "common.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_CHECK(expr)                                                                      \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(LINKS_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct links_ctx {
+  int device = 0;
+  int num_cu = 0;
+  std::map<std::string, Buf> bufs;
+  int table_T = 0;
+  std::vector<double> cs64_host;
+  std::vector<float> cs32_host;
+  // launch parameters (see links_set_tuning)
+  int waves32 = 1;
+  int refill_min = 8;
+  int waves64 = 1;
+  std::map<std::string, int> occ_cache;
+  // last call's statistics
+  int last_grid32 = 0, last_grid64 = 0;
+  // profiling: events around the passes of the last links_simulate
+  bool profile = false;
+  hipEvent_t ev[LINKS_TIMING_PASSES + 1] = {};
+  bool ev_used[LINKS_TIMING_PASSES] = {};
+  bool ev_ready = false;
+};
+
+namespace {
+
+int ensure(links_ctx* ctx, const char* name, size_t bytes, void** out) {
+  Buf& b = ctx->bufs[name];
+  if (b.bytes < bytes) {
+    if (b.p) {
+      hipError_t e = hipFree(b.p);
+      b.p = nullptr;
+      b.bytes = 0;
+      if (e != hipSuccess) return fail(LINKS_ERR_DEVICE, "hipFree(%s): %s", name, hipGetErrorString(e));
+    }
+    size_t want = bytes + bytes / 8 + 256;
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+      b.p = nullptr;
+      (void)hipGetLastError();
+      return fail(LINKS_ERR_OOM, "workspace allocation of %zu bytes for %s failed", want, name);
+    }
+    b.bytes = want;
+  }
+  *out = b.p;
+  return LINKS_OK;
+}
+
+template <typename T>
+int ensure_t(links_ctx* ctx, const char* name, size_t count, T** out) {
+  void* p = nullptr;
+  int rc = ensure(ctx, name, count * sizeof(T) + 16, &p);
+  *out = static_cast<T*>(p);
+  return rc;
+}
+
+int set_device(links_ctx* ctx) {
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return fail(LINKS_ERR_DEVICE, "hipSetDevice(%d): %s", ctx->device, hipGetErrorString(e));
+  return LINKS_OK;
+}
+
+int check_batch(const links_batch* b) {
+  if (!b) return fail(LINKS_ERR_ARG, "batch is NULL");
+  if (b->B < 0) return fail(LINKS_ERR_ARG, "B = %d < 0", b->B);
+  if (b->J < 1 || b->J > links::kMaxJ) return fail(LINKS_ERR_ARG, "J = %d outside [1, 32]", b->J);
+  if (b->B > 0 && (!b->n || !b->adj || !b->fixed || !b->motor))
+    return fail(LINKS_ERR_ARG, "batch has a NULL array");
+  return LINKS_OK;
+}
+
+// theta_t = 2 pi t / T, counter-clockwise, evaluated in double on the host
+int crank_table(links_ctx* ctx, int T, hipStream_t st, float2** cs32, double2** cs64) {
+  int rc = ensure_t(ctx, "cs64", (size_t)T, cs64);
+  if (rc) return rc;
+  rc = ensure_t(ctx, "cs32", (size_t)T, cs32);
+  if (rc) return rc;
+  if (ctx->table_T != T) {
+    ctx->cs64_host.resize(2 * (size_t)T);
+    ctx->cs32_host.resize(2 * (size_t)T);
+    for (int t = 0; t < T; t++) {
+      double theta = 2.0 * M_PI * (double)t / (double)T;
+      double c = cos(theta), s = sin(theta);
+      ctx->cs64_host[2 * t] = c;
+      ctx->cs64_host[2 * t + 1] = s;
+      ctx->cs32_host[2 * t] = (float)c;
+      ctx->cs32_host[2 * t + 1] = (float)s;
+    }
+    HIP_CHECK(hipMemcpyAsync(*cs64, ctx->cs64_host.data(), sizeof(double) * 2 * T, hipMemcpyHostToDevice, st));
+    HIP_CHECK(hipMemcpyAsync(*cs32, ctx->cs32_host.data(), sizeof(float) * 2 * T, hipMemcpyHostToDevice, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    ctx->table_T = T;
+  }
+  return LINKS_OK;
+}
+
+// records the boundary event before pass i (i == LINKS_TIMING_PASSES: after the last)
+int mark(links_ctx* ctx, int i, hipStream_t st) {
+  if (!ctx->profile) return LINKS_OK;
+  if (!ctx->ev[i]) HIP_CHECK(hipEventCreate(&ctx->ev[i]));
+  HIP_CHECK(hipEventRecord(ctx->ev[i], st));
+  return LINKS_OK;
+}
+
+int grid_for(links_ctx* ctx, const std::string& key, int per_cu) {
+  (void)key;
+  int g = ctx->num_cu * (per_cu > 0 ? per_cu : 1);
+  return g > 0 ? g : 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* links_last_error(void) { return g_err.c_str(); }
+
+const char* links_version(void) { return "links-mi355x 0.1 (gfx950)"; }
+
+int links_create(int device, links_ctx** out) {
+  if (!out) return fail(LINKS_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess) return fail(LINKS_ERR_DEVICE, "hipGetDeviceCount: %s", hipGetErrorString(e));
+  if (device < 0 || device >= count) return fail(LINKS_ERR_ARG, "device %d outside [0, %d)", device, count);
+  links_ctx* ctx = new links_ctx();
+  ctx->device = device;
+  int rc = set_device(ctx);
+  if (rc) {
+    delete ctx;
+    return rc;
+  }
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) {
+    delete ctx;
+    return fail(LINKS_ERR_DEVICE, "hipGetDeviceProperties: %s", hipGetErrorString(e));
+  }
+  ctx->num_cu = prop.multiProcessorCount;
+  *out = ctx;
+  return LINKS_OK;
+}
+
+void links_destroy(links_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  for (auto& e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& kv : ctx->bufs)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  delete ctx;
+}
+
+void links_sim_opts_default(links_sim_opts* o) {
+  if (!o) return;
+  o->T = 200;
+  o->precision = LINKS_FP32_RECHECK;
+  o->eps_disc = 1e-6;
+  o->eps_branch = 1e-5;
+  o->tau_drift = 1e-4;
+  o->out_joint = -1;
+  o->write = LINKS_WRITE_NONE;
+  o->path_dtype = LINKS_F32;
+}
+
+int links_set_tuning(links_ctx* ctx, int waves32, int refill_min, int waves64) {
+  if (!ctx) return fail(LINKS_ERR_ARG, "ctx is NULL");
+  if (waves32 < 1 || waves32 > 4 || waves64 < 1 || waves64 > 4 || refill_min < 1 || refill_min > 64)
+    return fail(LINKS_ERR_ARG, "tuning out of range (waves 1..4, refill_min 1..64)");
+  ctx->waves32 = waves32;
+  ctx->refill_min = refill_min;
+  ctx->waves64 = waves64;
+  return LINKS_OK;
+}
+
+int links_get_tuning(links_ctx* ctx, int* waves32, int* refill_min, int* waves64, int* grid32, int* grid64) {
+  if (!ctx) return fail(LINKS_ERR_ARG, "ctx is NULL");
+  if (waves32) *waves32 = ctx->waves32;
+  if (refill_min) *refill_min = ctx->refill_min;
+  if (waves64) *waves64 = ctx->waves64;
+  if (grid32) *grid32 = ctx->last_grid32;
+  if (grid64) *grid64 = ctx->last_grid64;
+  return LINKS_OK;
+}
+
+int links_solve_order(links_ctx* ctx, const links_batch* batch, int8_t* order, uint8_t* n_dyads, uint8_t* depth,
+                      uint8_t* status, void* stream) {
+  if (!ctx) return fail(LINKS_ERR_ARG, "ctx is NULL");
+  int rc = check_batch(batch);
+  if (rc) return rc;
+  if (batch->B > 0 && !status) return fail(LINKS_ERR_ARG, "status is NULL");
+  rc = set_device(ctx);
+  if (rc) return rc;
+  if (batch->B == 0) return LINKS_OK;
+  links::PrepArgs a;
+  memset(&a, 0, sizeof(a));
+  a.B = batch->B;
+  a.J = batch->J;
+  a.n = batch->n;
+  a.adj = batch->adj;
+  a.fixed = batch->fixed;
+  a.motor = batch->motor;
+  a.x0 = batch->x0;
+  a.order = order;
+  a.n_dyads = n_dyads;
+  a.depth = depth;
+  a.status = status;
+  a.sim = 0;
+  HIP_CHECK(links::launch_prep(a, (hipStream_t)stream));
+  return LINKS_OK;
+}
+
+int links_simulate(links_ctx* ctx, const links_batch* batch, const links_sim_opts* opts, links_sim_out* out,
+                   void* stream) {
+  if (!ctx) return fail(LINKS_ERR_ARG, "ctx is NULL");
+  int rc = check_batch(batch);
+  if (rc) return rc;
+  if (!opts || !out) return fail(LINKS_ERR_ARG, "opts or out is NULL");
+  const int B = batch->B, J = batch->J, T = opts->T;
+  if (T < 1 || T > 32767) return fail(LINKS_ERR_ARG, "T = %d outside [1, 32767]", T);
+  if (opts->precision < 0 || opts->precision > 2) return fail(LINKS_ERR_ARG, "bad precision %d", opts->precision);
+  if (opts->write < 0 || opts->write > 2) return fail(LINKS_ERR_ARG, "bad write mode %d", opts->write);
+  if (opts->path_dtype != LINKS_F32 && opts->path_dtype != LINKS_F64)
+    return fail(LINKS_ERR_ARG, "bad path dtype %d", opts->path_dtype);
+  if (opts->out_joint < -1 || opts->out_joint >= J) return fail(LINKS_ERR_ARG, "out_joint %d outside [-1, J)", opts->out_joint);
+  if (!(opts->eps_disc >= 0) || !(opts->eps_branch >= 0) || !(opts->tau_drift >= 0))
+    return fail(LINKS_ERR_ARG, "negative or NaN tolerance");
+  if (B > 0 && (!batch->x0 || !out->status)) return fail(LINKS_ERR_ARG, "x0 or status is NULL");
+  if (opts->write != LINKS_WRITE_NONE && B > 0 && !out->path && !(opts->write == LINKS_WRITE_VALID && out->cap == 0))
+    return fail(LINKS_ERR_ARG, "path is NULL");
+  if (opts->write == LINKS_WRITE_VALID && (out->cap < 0 || !out->n_written || (out->cap > 0 && !out->path_index)))
+    return fail(LINKS_ERR_ARG, "WRITE_VALID needs cap >= 0, n_written and path_index");
+  rc = set_device(ctx);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  if (B == 0) {
+    if (opts->write == LINKS_WRITE_VALID) HIP_CHECK(links::launch_fill_u32(out->n_written, 1, 0u, st));
+    return LINKS_OK;
+  }
+
+  using namespace links;
+  CandMeta* meta;
+  CandF32* cf;
+  CandF64* cd;
+  DyadF32* df;
+  DyadF64* dd;
+  float2* x0s;
+  uint8_t* sj;
+  int32_t* perm;
+  int32_t* counters;
+  EscEntry* esc;
+  float2* esc_pos;
+  int16_t* fail_ws;
+  int32_t* refine;
+  if ((rc = ensure_t(ctx, "refine", B, &refine))) return rc;
+  if ((rc = ensure_t(ctx, "meta", B, &meta)) || (rc = ensure_t(ctx, "cf", B, &cf)) ||
+      (rc = ensure_t(ctx, "cd", B, &cd)) || (rc = ensure_t(ctx, "df", (size_t)B * J, &df)) ||
+      (rc = ensure_t(ctx, "dd", (size_t)B * J, &dd)) || (rc = ensure_t(ctx, "x0s", (size_t)B * J, &x0s)) ||
+      (rc = ensure_t(ctx, "sj", (size_t)B * J, &sj)) || (rc = ensure_t(ctx, "perm", B, &perm)) ||
+      (rc = ensure_t(ctx, "counters", kCntSize, &counters)) || (rc = ensure_t(ctx, "esc", B, &esc)) ||
+      (rc = ensure_t(ctx, "esc_pos", (size_t)B * J, &esc_pos)) || (rc = ensure_t(ctx, "fail_ws", B, &fail_ws)))
+    return rc;
+  float2* cs32;
+  double2* cs64;
+  if ((rc = crank_table(ctx, T, st, &cs32, &cs64))) return rc;
+
+  const size_t elt = opts->path_dtype == LINKS_F64 ? sizeof(double2) : sizeof(float2);
+  void* path = nullptr;
+  if (opts->write == LINKS_WRITE_ALL) {
+    path = out->path;
+    HIP_CHECK(launch_fill_u32(path, (size_t)B * T * elt / 4, 0xFFFFFFFFu, st));  // NaN
+  } else if (opts->write == LINKS_WRITE_VALID) {
+    if ((rc = ensure(ctx, "staging", (size_t)B * T * elt, &path))) return rc;
+  }
+
+  HIP_CHECK(launch_fill_u32(counters, kCntSize, 0u, st));
+  int16_t* fail_step = out->fail_step ? out->fail_step : fail_ws;
+
+  PrepArgs pa;
+  memset(&pa, 0, sizeof(pa));
+  pa.B = B;
+  pa.J = J;
+  pa.n = batch->n;
+  pa.adj = batch->adj;
+  pa.fixed = batch->fixed;
+  pa.motor = batch->motor;
+  pa.x0 = batch->x0;
+  pa.status = out->status;
+  pa.sim = 1;
+  pa.out_joint = opts->out_joint;
+  pa.eps_disc = opts->eps_disc;
+  pa.eps_branch = opts->eps_branch;
+  pa.tau_drift = opts->tau_drift;
+  pa.path_tol = 1e-5;
+  pa.fail_step = fail_step;
+  pa.esc_step = out->esc_step;
+  pa.meta = meta;
+  pa.cf = cf;
+  pa.cd = cd;
+  pa.df = df;
+  pa.dd = dd;
+  pa.x0s = x0s;
+  pa.slot_joint = sj;
+  pa.counters = counters;
+  for (int i = 0; i < LINKS_TIMING_PASSES; i++) ctx->ev_used[i] = false;
+  ctx->ev_ready = false;
+  if ((rc = mark(ctx, 0, st))) return rc;
+  HIP_CHECK(launch_prep(pa, st));
+  ctx->ev_used[0] = true;
+  if ((rc = mark(ctx, 1, st))) return rc;
+  HIP_CHECK(launch_bucket_sort(B, out->status, meta, counters, perm, st));
+  ctx->ev_used[1] = true;
+  if ((rc = mark(ctx, 2, st))) return rc;
+
+  SimArgs sa;
+  memset(&sa, 0, sizeof(sa));
+  sa.B = B;
+  sa.J = J;
+  sa.T = T;
+  sa.n = batch->n;
+  sa.adj = batch->adj;
+  sa.fixed = batch->fixed;
+  sa.motor = batch->motor;
+  sa.x0 = batch->x0;
+  sa.meta = meta;
+  sa.cf = cf;
+  sa.cd = cd;
+  sa.df = df;
+  sa.dd = dd;
+  sa.x0s = x0s;
+  sa.slot_joint = sj;
+  sa.perm = perm;
+  sa.counters = counters;
+  sa.esc = esc;
+  sa.esc_pos = esc_pos;
+  sa.refine = refine;
+  sa.write_all = opts->write == LINKS_WRITE_ALL;
+  sa.cs32 = cs32;
+  sa.cs64 = cs64;
+  sa.status = out->status;
+  sa.fail_step = fail_step;
+  sa.esc_step = out->esc_step;
+  sa.path = path;
+  sa.path_f64 = opts->path_dtype == LINKS_F64;
+  sa.nslot = J;
+  sa.refill_min = ctx->refill_min;
+
+  LaunchCfg c64;
+  c64.waves = ctx->waves64;
+  c64.refill_min = 1;
+  const int lds64 = sim64_lds_bytes(J, c64.waves);
+  const int source = opts->precision == LINKS_FP64 ? kFromPerm : kFromEsc;
+  c64.grid = grid_for(ctx, "sim64", sim64_blocks_per_cu(J, source, c64.waves, lds64));
+  if (opts->precision == LINKS_FP64) {
+    if ((rc = mark(ctx, 3, st))) return rc;
+    HIP_CHECK(launch_sim64(sa, kFromPerm, c64, st));
+    ctx->ev_used[3] = true;
+    if ((rc = mark(ctx, 4, st))) return rc;
+    ctx->last_grid32 = 0;
+  } else {
+    LaunchCfg c32;
+    c32.waves = ctx->waves32;
+    c32.refill_min = ctx->refill_min;
+    const int mode = opts->precision == LINKS_FP32_ONLY ? 1 : 0;
+    const int lds32 = sim32_lds_bytes(J, c32.waves);
+    c32.grid = grid_for(ctx, "sim32", sim32_blocks_per_cu(J, mode, c32.waves, lds32));
+    HIP_CHECK(launch_sim32(sa, mode, c32, st));
+    ctx->ev_used[2] = true;
+    if ((rc = mark(ctx, 3, st))) return rc;
+    HIP_CHECK(launch_sim64(sa, kFromEsc, c64, st));
+    ctx->ev_used[3] = true;
+    if ((rc = mark(ctx, 4, st))) return rc;
+    if (path != nullptr && mode == 0) {
+      HIP_CHECK(launch_sim64(sa, kFromRefine, c64, st));
+      ctx->ev_used[4] = true;
+    }
+    ctx->last_grid32 = c32.grid;
+  }
+  ctx->last_grid64 = c64.grid;
+
+  if ((rc = mark(ctx, 5, st))) return rc;
+  if (opts->write == LINKS_WRITE_VALID) {
+    ctx->ev_used[5] = true;
+    int32_t* scratch;
+    if ((rc = ensure_t(ctx, "compact", compact_scratch_ints(B), &scratch))) return rc;
+    HIP_CHECK(launch_compact(B, out->status, scratch, out->path_index, out->cap, out->n_written, st));
+    if (out->cap > 0)
+      HIP_CHECK(launch_gather_rows(out->path_index, out->n_written, out->cap, path, out->path, (size_t)T * elt, st));
+  }
+  if ((rc = mark(ctx, 6, st))) return rc;
+  ctx->ev_ready = ctx->profile;
+  return LINKS_OK;
+}
+
+int links_profile(links_ctx* ctx, int enable) {
+  if (!ctx) return fail(LINKS_ERR_ARG, "ctx is NULL");
+  ctx->profile = enable != 0;
+  ctx->ev_ready = false;
+  return LINKS_OK;
+}
+
+int links_last_timings(links_ctx* ctx, float* ms, int n) {
+  if (!ctx || (!ms && n > 0)) return fail(LINKS_ERR_ARG, "NULL argument");
+  if (!ctx->ev_ready) return fail(LINKS_ERR_ARG, "no profiled links_simulate call");
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  HIP_CHECK(hipEventSynchronize(ctx->ev[LINKS_TIMING_PASSES]));
+  int k = n < LINKS_TIMING_PASSES ? n : LINKS_TIMING_PASSES;
+  for (int i = 0; i < k; i++) {
+    ms[i] = 0.f;
+    if (ctx->ev_used[i]) HIP_CHECK(hipEventElapsedTime(&ms[i], ctx->ev[i], ctx->ev[i + 1]));
+  }
+  return k;
+}
+
+int links_normalize_paths(links_ctx* ctx, const float* paths, int32_t P, int32_t T, int32_t mode, float* out,
+                          float* xform, void* stream) {
+  if (!ctx) return fail(LINKS_ERR_ARG, "ctx is NULL");
+  if (P < 0) return fail(LINKS_ERR_ARG, "P = %d < 0", P);
+  if (T < 1 || T > 4096) return fail(LINKS_ERR_ARG, "T = %d outside [1, 4096]", T);
+  if (mode != LINKS_NORM_PCA && mode != LINKS_NORM_DIAMETER) return fail(LINKS_ERR_ARG, "bad mode %d", mode);
+  if (P > 0 && (!paths || !out || !xform)) return fail(LINKS_ERR_ARG, "NULL array");
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  HIP_CHECK(links::launch_normalize(paths, P, nullptr, T, mode, out, xform, (hipStream_t)stream));
+  return LINKS_OK;
+}
+
+int links_normalize_paths_n(links_ctx* ctx, const float* paths, const int32_t* count, int32_t cap, int32_t T,
+                            int32_t mode, float* out, float* xform, void* stream) {
+  if (!ctx) return fail(LINKS_ERR_ARG, "ctx is NULL");
+  if (cap < 0) return fail(LINKS_ERR_ARG, "cap = %d < 0", cap);
+  if (T < 1 || T > 4096) return fail(LINKS_ERR_ARG, "T = %d outside [1, 4096]", T);
+  if (mode != LINKS_NORM_PCA && mode != LINKS_NORM_DIAMETER) return fail(LINKS_ERR_ARG, "bad mode %d", mode);
+  if (cap > 0 && (!paths || !out || !xform || !count)) return fail(LINKS_ERR_ARG, "NULL array");
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  HIP_CHECK(links::launch_normalize(paths, cap, count, T, mode, out, xform, (hipStream_t)stream));
+  return LINKS_OK;
+}
+
+}  // extern "C"

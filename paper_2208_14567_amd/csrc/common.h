@@ -1,0 +1,113 @@
+// common.h -- internal definitions shared by the kernels and the host runtime of
+// liblinks.so.  Nothing here is part of the public ABI (include/links.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace links {
+
+constexpr int kMaxJ = 32;
+constexpr int kWave = 64;
+
+// internal status of a candidate that still has to be simulated
+constexpr uint8_t kPending = 255;
+
+// per-candidate flags written by the prep kernel
+constexpr uint32_t kFlagRedundant = 1u;  // has links outside the solve order (drift checks)
+constexpr uint32_t kFlagNoPath = 2u;     // requested output joint does not exist
+
+// ---------------------------------------------------------------------------
+// Per-candidate records produced once per mechanism by the prep kernel.  Slots
+// are the LDS positions used during simulation: joint of solve-order entry s is
+// in slot s, the tip in slot D, the fixed joints after it in ascending index.
+struct CandMeta {
+  uint8_t D;         // placed joints (solve-order entries)
+  uint8_t n;         // joints
+  uint8_t out_slot;  // slot of the output joint
+  uint8_t flags;     // kFlag*
+};
+
+// FP32 constants of one candidate (thresholds are already scaled)
+struct CandF32 {
+  float px, py;  // pivot
+  float vx, vy;  // tip - pivot at t = 0
+  float U;       // rounding-error unit of a computed position
+  float KB;      // escalation band on K: 4 eps_disc scale^4
+  float CD;      // escalation band on d^2: eps_disc scale^2
+  float EB;      // escalation band on the branch distance: eps_branch scale
+  float EP;      // largest tolerated path error: path_tol scale
+  float U2;      // rounding of one placement relative to the link lengths: u 2 scale
+  float TS;      // 2 scale, a bound on 2 ra in the branch error term
+  float u;       // relative rounding unit of a placement
+  float DG;      // degenerate threshold 1e-12 scale^2 (FP32-only mode)
+  float pad[3];
+};
+
+// FP64 constants of one candidate
+struct CandF64 {
+  double px, py, vx, vy;
+  double scale;
+  double deg_thr;  // 1e-12 scale^2
+  double drift_thr;  // tau scale
+  double pad;
+};
+
+// FP32 per-entry constants, rounded from FP64: S = (ra + rb)^2, Dm = (ra - rb)^2,
+// Kc = (ra^2 - rb^2)/2; parent slots packed as a | b << 8.
+struct DyadF32 {
+  float S, Dm, Kc;
+  uint32_t slots;
+};
+
+// FP64 per-entry constants, computed exactly as the reference arithmetic does
+struct DyadF64 {
+  double ra2, rb2;  // squared initial link lengths to parents a and b
+  double S, Dm;     // (ra + rb)^2 and (ra - rb)^2 with ra = sqrt(ra2), rb = sqrt(rb2)
+};
+
+// A candidate handed from the FP32 pass to the FP64 pass.
+struct EscEntry {
+  int32_t cand;
+  int16_t t;      // step to recompute in FP64
+  int8_t from_x0;    // 1: start from x0 at step 0 (links outside the solve order)
+  int8_t path_bad;   // 1: the FP32 steps before t exceeded the path error bound
+};
+
+// Pointers of the workspace and of the caller's batch, passed by value to kernels.
+struct SimArgs {
+  // batch
+  int32_t B, J, T;
+  const uint8_t* n;
+  const uint32_t* adj;
+  const uint32_t* fixed;
+  const uint8_t* motor;
+  const double* x0;
+  // records
+  CandMeta* meta;
+  CandF32* cf;
+  CandF64* cd;
+  DyadF32* df;      // [B][J]
+  DyadF64* dd;      // [B][J]
+  float2* x0s;      // [B][J] initial positions in slot order (FP32)
+  uint8_t* slot_joint;  // [B][J] joint in each slot
+  // scheduling
+  int32_t* perm;    // [B] candidates to simulate, largest D first
+  int32_t* counters;  // [0] next work item, [1] work items, [2] escalations, [3] next esc item, [4..] D histogram
+  EscEntry* esc;    // [B]
+  int32_t* refine;  // [B] candidates whose path is recomputed in FP64
+  int32_t write_all;  // every candidate's path is output (else only valid ones)
+  float2* esc_pos;  // [B][J] FP32 slot positions at hand-over
+  // crank table
+  const float2* cs32;   // [T] (cos, sin) rounded from FP64
+  const double2* cs64;  // [T]
+  // outputs
+  uint8_t* status;
+  int16_t* fail_step;
+  int16_t* esc_step;
+  void* path;          // [rows][T][2] or null
+  int32_t path_f64;    // element type
+  int32_t nslot;       // LDS slots per lane (max n)
+  int32_t refill_min;  // refill a wave when at least this many lanes are idle
+};
+
+}  // namespace links

@@ -1,0 +1,81 @@
+// kernels.h -- launchers of the device kernels (internal to liblinks.so).
+#pragma once
+#include "common.h"
+
+namespace links {
+
+// counters[] layout (int32 in device memory)
+constexpr int kCntNext = 0;     // next work item of the simulation pass
+constexpr int kCntItems = 1;    // work items of the simulation pass
+constexpr int kCntEsc = 2;      // candidates handed to FP64
+constexpr int kCntEscNext = 3;  // next hand-over item taken by the FP64 pass
+constexpr int kCntValid = 4;    // valid candidates (compaction)
+constexpr int kCntRefine = 5;   // candidates whose FP32 path must be recomputed in FP64
+constexpr int kCntRefineNext = 6;
+constexpr int kCntHist = 8;     // [32] histogram of solve-order lengths
+constexpr int kCntOff = 40;     // [32] bucket offsets
+constexpr int kCntSize = 72;
+
+struct PrepArgs {
+  int32_t B, J;
+  const uint8_t* n;
+  const uint32_t* adj;
+  const uint32_t* fixed;
+  const uint8_t* motor;
+  const double* x0;
+  // solve-order outputs (nullable)
+  int8_t* order;
+  uint8_t* n_dyads;
+  uint8_t* depth;
+  uint8_t* status;
+  // simulation records (sim != 0)
+  int32_t sim;
+  int32_t out_joint;
+  double eps_disc, eps_branch, tau_drift, path_tol;
+  int16_t* fail_step;
+  int16_t* esc_step;
+  CandMeta* meta;
+  CandF32* cf;
+  CandF64* cd;
+  DyadF32* df;
+  DyadF64* dd;
+  float2* x0s;
+  uint8_t* slot_joint;
+  int32_t* counters;
+};
+
+hipError_t launch_prep(const PrepArgs& a, hipStream_t st);
+hipError_t launch_bucket_sort(int32_t B, const uint8_t* status, const CandMeta* meta, int32_t* counters,
+                              int32_t* perm, hipStream_t st);
+hipError_t launch_fill_u32(void* p, size_t n_u32, uint32_t v, hipStream_t st);
+size_t compact_scratch_ints(int32_t B);
+hipError_t launch_compact(int32_t B, const uint8_t* status, int32_t* scratch, int32_t* index, int32_t cap,
+                          int32_t* total, hipStream_t st);
+hipError_t launch_gather_rows(const int32_t* index, const int32_t* total, int32_t cap, const void* staged,
+                              void* out, size_t row_bytes, hipStream_t st);
+
+// Simulation passes.  `grid` = persistent workgroups; block = waves * 64 lanes.
+struct LaunchCfg {
+  int grid;
+  int waves;
+  int refill_min;
+};
+// FP32 pass: mode 0 escalates to FP64, mode 1 never escalates.
+hipError_t launch_sim32(const SimArgs& a, int mode, const LaunchCfg& cfg, hipStream_t st);
+int sim32_lds_bytes(int nslot, int waves);
+int sim32_dmax(int J);
+// FP64 pass work sources
+constexpr int kFromPerm = 0;    // every pending candidate from t = 0 (plain FP64 precision)
+constexpr int kFromEsc = 1;     // candidates handed over by the FP32 pass, from their step
+constexpr int kFromRefine = 2;  // candidates whose FP32 path exceeded its error bound, from t = 0
+hipError_t launch_sim64(const SimArgs& a, int source, const LaunchCfg& cfg, hipStream_t st);
+int sim64_lds_bytes(int nslot, int waves);
+// occupancy helper: resident workgroups per CU for a kernel variant
+int sim32_blocks_per_cu(int J, int mode, int waves, int lds_bytes);
+int sim64_blocks_per_cu(int J, int source, int waves, int lds_bytes);
+
+// Path normalisation, one wave per path.
+hipError_t launch_normalize(const float* paths, int32_t P, const int32_t* count, int32_t T, int32_t mode,
+                            float* out, float* xform, hipStream_t st);
+
+}  // namespace links

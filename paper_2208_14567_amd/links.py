@@ -1,0 +1,257 @@
+"""Python binding of liblinks.so (argument marshalling only).
+
+Every step of the simulation runs in the HIP library; this module only moves
+torch device tensors' pointers and the current HIP stream across the C ABI of
+``include/links.h``.  It raises if the library is not built -- there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblinks.so")
+
+OK, ERR_ARG, ERR_DEVICE, ERR_OOM = 0, -1, -2, -3
+VALID, LOCKED, DEGENERATE, DRIFT, UNSOLVABLE, BAD_MECH = range(6)
+FP32_RECHECK, FP64, FP32_ONLY = 0, 1, 2
+WRITE_NONE, WRITE_ALL, WRITE_VALID = 0, 1, 2
+F32, F64 = 0, 1
+NORM_PCA, NORM_DIAMETER = 0, 1
+NF_CONSTANT, NF_ISOTROPIC, NF_SIGN_TIE, NF_DIAM_TIE = 1, 2, 4, 8
+
+P = ctypes.c_void_p
+i32 = ctypes.c_int32
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [("B", i32), ("J", i32), ("n", P), ("adj", P), ("fixed", P), ("motor", P), ("x0", P)]
+
+
+class SimOpts(ctypes.Structure):
+    _fields_ = [("T", i32), ("precision", i32), ("eps_disc", ctypes.c_double), ("eps_branch", ctypes.c_double),
+                ("tau_drift", ctypes.c_double), ("out_joint", i32), ("write", i32), ("path_dtype", i32)]
+
+
+class SimOut(ctypes.Structure):
+    _fields_ = [("status", P), ("fail_step", P), ("esc_step", P), ("path", P), ("path_index", P),
+                ("n_written", P), ("cap", i32)]
+
+
+EXPORTS = ["links_create", "links_destroy", "links_last_error", "links_version", "links_solve_order",
+           "links_sim_opts_default", "links_simulate", "links_normalize_paths", "links_set_tuning",
+           "links_get_tuning", "links_normalize_paths_n", "links_profile", "links_last_timings"]
+TIMING_PASSES = ["prep", "bucket_sort", "fp32_pass", "fp64_pass", "fp64_path_pass", "compaction"]
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Loads liblinks.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                           "python -m paper_2208_14567_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    L.links_create.argtypes = [ctypes.c_int, ctypes.POINTER(P)]
+    L.links_create.restype = ctypes.c_int
+    L.links_destroy.argtypes = [P]
+    L.links_destroy.restype = None
+    L.links_last_error.argtypes = []
+    L.links_last_error.restype = ctypes.c_char_p
+    L.links_version.argtypes = []
+    L.links_version.restype = ctypes.c_char_p
+    L.links_solve_order.argtypes = [P, ctypes.POINTER(Batch), P, P, P, P, P]
+    L.links_solve_order.restype = ctypes.c_int
+    L.links_sim_opts_default.argtypes = [ctypes.POINTER(SimOpts)]
+    L.links_sim_opts_default.restype = None
+    L.links_simulate.argtypes = [P, ctypes.POINTER(Batch), ctypes.POINTER(SimOpts), ctypes.POINTER(SimOut), P]
+    L.links_simulate.restype = ctypes.c_int
+    L.links_normalize_paths.argtypes = [P, P, i32, i32, i32, P, P, P]
+    L.links_normalize_paths.restype = ctypes.c_int
+    L.links_set_tuning.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.links_set_tuning.restype = ctypes.c_int
+    L.links_get_tuning.argtypes = [P] + [ctypes.POINTER(ctypes.c_int)] * 5
+    L.links_get_tuning.restype = ctypes.c_int
+    L.links_normalize_paths_n.argtypes = [P, P, P, i32, i32, i32, P, P, P]
+    L.links_normalize_paths_n.restype = ctypes.c_int
+    L.links_profile.argtypes = [P, ctypes.c_int]
+    L.links_profile.restype = ctypes.c_int
+    L.links_last_timings.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
+    L.links_last_timings.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+class LinksError(RuntimeError):
+    pass
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        msg = load().links_last_error().decode(errors="replace")
+        raise LinksError(f"{what} failed ({rc}): {msg}")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class DeviceBatch:
+    """Device copies of a batch (layout of include/links.h)."""
+    n: torch.Tensor
+    adj: torch.Tensor
+    fixed: torch.Tensor
+    motor: torch.Tensor
+    x0: torch.Tensor
+
+    @property
+    def B(self) -> int:
+        return int(self.n.shape[0])
+
+    @property
+    def J(self) -> int:
+        return int(self.adj.shape[1]) if self.adj.dim() == 2 else 1
+
+    def cstruct(self) -> Batch:
+        return Batch(self.B, self.J, _ptr(self.n), _ptr(self.adj), _ptr(self.fixed), _ptr(self.motor), _ptr(self.x0))
+
+    def slice(self, lo: int, hi: int) -> "DeviceBatch":
+        return DeviceBatch(self.n[lo:hi], self.adj[lo:hi], self.fixed[lo:hi], self.motor[lo:hi], self.x0[lo:hi])
+
+
+def to_device(batch, device="cuda", non_blocking=False) -> DeviceBatch:
+    """Copies a host batch (paper_2208_14567_amd.gen.Batch) to the device."""
+    def t(a, dtype):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).to(device, non_blocking=non_blocking)
+    return DeviceBatch(t(batch.n, np.uint8), t(batch.adj.view(np.int32), np.int32), t(batch.fixed.view(np.int32), np.int32),
+                       t(batch.motor, np.uint8), t(batch.x0, np.float64))
+
+
+class Context:
+    """A library context bound to one HIP device."""
+
+    def __init__(self, device: int = 0):
+        L = load()
+        h = P()
+        _check(L.links_create(device, ctypes.byref(h)), "links_create")
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().links_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tuning(self, waves32: int, refill_min: int, waves64: int):
+        _check(load().links_set_tuning(self._h, waves32, refill_min, waves64), "links_set_tuning")
+
+    def get_tuning(self) -> dict:
+        v = [ctypes.c_int() for _ in range(5)]
+        _check(load().links_get_tuning(self._h, *[ctypes.byref(x) for x in v]), "links_get_tuning")
+        return dict(zip(["waves32", "refill_min", "waves64", "grid32", "grid64"], [x.value for x in v]))
+
+    def profile(self, enable: bool = True):
+        _check(load().links_profile(self._h, 1 if enable else 0), "links_profile")
+
+    def last_timings(self) -> dict:
+        """Milliseconds of each pass of the last profiled simulate call."""
+        n = len(TIMING_PASSES)
+        buf = (ctypes.c_float * n)()
+        k = load().links_last_timings(self._h, buf, n)
+        if k < 0:
+            _check(k, "links_last_timings")
+        return {name: float(buf[i]) for i, name in enumerate(TIMING_PASSES[:k])}
+
+    # ------------------------------------------------------------------ solve order
+    def solve_order(self, b: DeviceBatch, stream=None):
+        dev = b.n.device
+        order = torch.empty((b.B, b.J, 3), dtype=torch.int8, device=dev)
+        nd = torch.empty(b.B, dtype=torch.uint8, device=dev)
+        dp = torch.empty(b.B, dtype=torch.uint8, device=dev)
+        st = torch.empty(b.B, dtype=torch.uint8, device=dev)
+        cb = b.cstruct()
+        _check(load().links_solve_order(self._h, ctypes.byref(cb), _ptr(order), _ptr(nd), _ptr(dp), _ptr(st),
+                                        _stream(stream)), "links_solve_order")
+        return order, nd, dp, st
+
+    # ------------------------------------------------------------------ simulation
+    def simulate(self, b: DeviceBatch, T: int = 200, precision: int = FP32_RECHECK, write: int = WRITE_NONE,
+                 out_joint: int = -1, path_dtype: int = F32, cap: Optional[int] = None, eps_disc: float = 1e-6,
+                 eps_branch: float = 1e-5, tau_drift: float = 1e-4, out: Optional[dict] = None, stream=None):
+        """Returns a dict of device tensors: status, fail_step, esc_step and, by write
+        mode, path ([B,T,2] or [cap,T,2]), path_index and n_written."""
+        dev = b.n.device
+        B = b.B
+        o = out or {}
+        status = o.get("status") if o.get("status") is not None else torch.empty(B, dtype=torch.uint8, device=dev)
+        fail = o.get("fail_step") if o.get("fail_step") is not None else torch.empty(B, dtype=torch.int16, device=dev)
+        esc = o.get("esc_step") if o.get("esc_step") is not None else torch.empty(B, dtype=torch.int16, device=dev)
+        pdt = torch.float64 if path_dtype == F64 else torch.float32
+        path = idx = nw = None
+        cap_v = 0
+        if write == WRITE_ALL:
+            path = o.get("path") if o.get("path") is not None else torch.empty((B, T, 2), dtype=pdt, device=dev)
+        elif write == WRITE_VALID:
+            cap_v = B if cap is None else int(cap)
+            path = o.get("path") if o.get("path") is not None else torch.empty((max(cap_v, 1), T, 2), dtype=pdt, device=dev)
+            idx = o.get("path_index") if o.get("path_index") is not None else torch.empty(max(cap_v, 1), dtype=torch.int32, device=dev)
+            nw = o.get("n_written") if o.get("n_written") is not None else torch.empty(1, dtype=torch.int32, device=dev)
+        opts = SimOpts(T, precision, eps_disc, eps_branch, tau_drift, out_joint, write, path_dtype)
+        so = SimOut(_ptr(status), _ptr(fail), _ptr(esc), _ptr(path), _ptr(idx), _ptr(nw), cap_v)
+        cb = b.cstruct()
+        _check(load().links_simulate(self._h, ctypes.byref(cb), ctypes.byref(opts), ctypes.byref(so), _stream(stream)),
+               "links_simulate")
+        res = {"status": status, "fail_step": fail, "esc_step": esc}
+        if path is not None:
+            res["path"] = path
+        if idx is not None:
+            res["path_index"] = idx
+            res["n_written"] = nw
+        return res
+
+    # ------------------------------------------------------------------ normalisation
+    def normalize_paths(self, paths: torch.Tensor, mode: int = NORM_PCA, out: Optional[torch.Tensor] = None,
+                        xform: Optional[torch.Tensor] = None, stream=None):
+        if paths.dtype != torch.float32:
+            raise ValueError("paths must be float32")
+        Pn, T = int(paths.shape[0]), int(paths.shape[1])
+        out = torch.empty_like(paths) if out is None else out
+        xform = torch.empty((Pn, 5), dtype=torch.float32, device=paths.device) if xform is None else xform
+        _check(load().links_normalize_paths(self._h, _ptr(paths), Pn, T, mode, _ptr(out), _ptr(xform), _stream(stream)),
+               "links_normalize_paths")
+        return out, xform
+
+    def normalize_paths_n(self, paths: torch.Tensor, count: torch.Tensor, mode: int = NORM_PCA,
+                          out: Optional[torch.Tensor] = None, xform: Optional[torch.Tensor] = None, stream=None):
+        """Normalises the first min(count[0], len(paths)) rows; count is a device int32."""
+        cap, T = int(paths.shape[0]), int(paths.shape[1])
+        out = torch.empty_like(paths) if out is None else out
+        xform = torch.empty((cap, 5), dtype=torch.float32, device=paths.device) if xform is None else xform
+        _check(load().links_normalize_paths_n(self._h, _ptr(paths), _ptr(count), cap, T, mode, _ptr(out), _ptr(xform),
+                                              _stream(stream)), "links_normalize_paths_n")
+        return out, xform

@@ -1,0 +1,283 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bars (element by element, same seeded inputs):
+* solve order, n_dyads, depth, status of links_solve_order: bit-exact;
+* FP64 precision: status and fail_step bit-exact for every candidate, paths
+  bit-exact (the FP64 pass evaluates the same correctly rounded operations);
+* FP32 with escalation: status and fail_step bit-exact for every candidate whose
+  oracle margins are outside the bands (|disc| >= 1e-6 scale^2, d^2 >= 1e-6
+  scale^2, branch distance >= 1e-5 scale, drift margin >= 0.9e-4 scale); paths
+  within 1e-5 scale at every written step.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2208_14567_amd import gen
+from tests import mech
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+NTH = min(16, os.cpu_count() or 1)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2208_14567_amd import links
+    return links
+
+
+@pytest.fixture(scope="module")
+def ctx(L):
+    return L.Context(0)
+
+
+def _np(r):
+    return {k: v.cpu().numpy() for k, v in r.items()}
+
+
+def _scale(b):
+    return mech.scale_of(b)
+
+
+WORKLOADS = [("fourbar", 4000, 1), ("fourbar_u", 4000, 11), ("dyad_6_20", 20000, 2), ("dyad_skewed", 20000, 3),
+             ("dyad_4_20", 8000, 4), ("paper_8_20", 6000, 6)]
+
+
+@pytest.mark.parametrize("name,B,seed", WORKLOADS)
+def test_solve_order_bit_exact(ctx, L, name, B, seed):
+    _say(f"[solve_order] {name} B={B}")
+    b = gen.workload(name, B, seed=seed)
+    o, nd, dp, st = ctx.solve_order(L.to_device(b))
+    ro, rnd, rdp, rst = oracle.solve_order(b)
+    assert np.array_equal(o.cpu().numpy(), ro)
+    assert np.array_equal(nd.cpu().numpy(), rnd) and np.array_equal(dp.cpu().numpy(), rdp)
+    assert np.array_equal(st.cpu().numpy(), rst)
+
+
+def _fixtures():
+    rng = np.random.default_rng(0)
+    FB = [(0, 1), (1, 3), (2, 3)]
+    X = [[0, 0], [1, 0], [4, 0], [11 / 3, 4 * 5 ** 0.5 / 3]]
+    ms = [
+        {"n": 4, "edges": FB + [(1, 2)], "fixed": [0, 2], "x0": X},                       # drift at step 1
+        {"n": 5, "edges": FB + [(0, 4), (1, 4), (3, 4)], "fixed": [0, 2], "x0": X + [[0.5, 0.8]]},
+        {"n": 4, "edges": FB, "fixed": [0, 2], "x0": [[0, 0], [1, 0], [0, 1], [0.5, 0.5]]},  # degenerate
+        {"n": 4, "edges": FB, "fixed": [0, 2], "x0": [[0, 0], [1, 0], [2.5, 0], [1.75, 0.6614378277661477]]},
+        {"n": 6, "edges": [(0, 1), (1, 3), (2, 4), (0, 5), (3, 4), (4, 5), (3, 5)], "fixed": [0, 2],
+         "x0": rng.random((6, 2))},                                                      # unsolvable
+        {"n": 4, "edges": FB, "fixed": [0, 2], "x0": [[0, 0], [1, 0], [4, 0], [1, 0]]},   # zero-length link
+        {"n": 5, "edges": [(0, 1), (0, 3), (1, 3), (0, 4), (1, 4), (3, 4)], "fixed": [0, 2],
+         "x0": [[0, 0], [1, 0], [5, 5], [0.3, 0.9], [0.8, -0.6]]},                       # consistent redundancy
+        {"n": 3, "edges": [(0, 1)], "fixed": [0, 2], "x0": [[0, 0], [1, 0], [2, 2]]},     # no placed joints
+    ]
+    b = mech.build(ms, J=8)
+    b.adj[5] = b.adj[5]
+    return b
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_status_fixtures(ctx, L, precision):
+    _say(f"[fixtures] precision={precision}")
+    b = _fixtures()
+    for T in (4, 8, 200):
+        r = _np(ctx.simulate(L.to_device(b), T=T, precision=precision, write=L.WRITE_ALL, path_dtype=L.F64))
+        ref = oracle.simulate(b, T=T, path=True)
+        assert np.array_equal(r["status"], ref["status"]), (T, r["status"], ref["status"])
+        assert np.array_equal(r["fail_step"], ref["fail_step"])
+        assert np.array_equal(np.isnan(r["path"]), np.isnan(ref["path"]))
+        tol = 1e-12 if precision == 1 else 1e-5 * _scale(b).max()
+        assert np.allclose(r["path"], ref["path"], rtol=0, atol=tol, equal_nan=True)
+
+
+@pytest.mark.parametrize("name,B,seed", WORKLOADS)
+def test_fp64_bit_exact(ctx, L, name, B, seed):
+    _say(f"[fp64] {name} B={B}")
+    b = gen.workload(name, B, seed=seed)
+    r = _np(ctx.simulate(L.to_device(b), T=200, precision=L.FP64, write=L.WRITE_ALL, path_dtype=L.F64))
+    ref = oracle.simulate(b, T=200, path=True, nthreads=NTH)
+    assert np.array_equal(r["status"], ref["status"])
+    assert np.array_equal(r["fail_step"], ref["fail_step"])
+    same = (r["path"] == ref["path"]) | (np.isnan(r["path"]) & np.isnan(ref["path"]))
+    assert same.all(), f"{(~same.all(axis=(1, 2))).sum()} paths differ in some bit"
+
+
+def _fp32_parity(ctx, L, b, T=200, write=None, label=""):
+    write = L.WRITE_ALL if write is None else write
+    r = _np(ctx.simulate(L.to_device(b), T=T, precision=L.FP32_RECHECK, write=write))
+    ref = oracle.simulate(b, T=T, path=True, margins=True, nthreads=NTH)
+    ib = oracle.in_band(ref["margins"])
+    clear = ~ib
+    bad = clear & ((r["status"] != ref["status"]) | (r["fail_step"] != ref["fail_step"]))
+    agree_in = ((r["status"] == ref["status"]) & (r["fail_step"] == ref["fail_step"]))[ib].mean() if ib.any() else 1.0
+    esc = (r["esc_step"] >= 0).mean()
+    _say(f"   {label}: out-of-band {clear.sum()} mismatches {bad.sum()}; in-band {ib.sum()} agree {agree_in:.3f}; "
+         f"handed to FP64 {esc:.3%}")
+    assert bad.sum() == 0, np.nonzero(bad)[0][:10]
+    if write == L.WRITE_ALL:
+        sc = _scale(b)
+        ok = clear & (ref["status"] == r["status"]) & (ref["fail_step"] == r["fail_step"])
+        nan_r, nan_o = np.isnan(r["path"][ok]), np.isnan(ref["path"][ok])
+        assert np.array_equal(nan_r, nan_o)
+        err = np.where(nan_o, 0.0, np.abs(r["path"][ok] - ref["path"][ok])).max(axis=(1, 2))
+        assert np.all(err <= 1e-5 * sc[ok]), (err / sc[ok]).max()
+        _say(f"   {label}: max path error / scale {(err / sc[ok]).max():.2e}")
+    return r, ref
+
+
+@pytest.mark.parametrize("name,B,seed", WORKLOADS)
+def test_fp32_recheck_parity(ctx, L, name, B, seed):
+    _say(f"[fp32r] {name} B={B}")
+    b = gen.workload(name, B, seed=seed)
+    _fp32_parity(ctx, L, b, label=name)
+
+
+@pytest.mark.parametrize("T", [1, 2, 50, 333])
+def test_step_counts(ctx, L, T):
+    _say(f"[T] {T}")
+    b = gen.Batch.concat([gen.workload("fourbar_u", 1000, seed=5), gen.workload("dyad_6_20", 3000, seed=5)])
+    _fp32_parity(ctx, L, b, T=T, label=f"T={T}")
+
+
+def test_ragged_and_wide_strides(ctx, L):
+    _say("[strides]")
+    for J, lo, hi in ((7, 4, 7), (13, 6, 13), (32, 20, 32)):
+        b = gen.dyad_batch(3000, 77 + J, gen.n_uniform(lo, hi), J=J)
+        _fp32_parity(ctx, L, b, label=f"J={J}")
+        r = _np(ctx.simulate(L.to_device(b), precision=L.FP64))
+        ref = oracle.simulate(b, nthreads=NTH)
+        assert np.array_equal(r["status"], ref["status"]) and np.array_equal(r["fail_step"], ref["fail_step"])
+
+
+def test_empty_and_single(ctx, L):
+    b = gen.workload("dyad_6_20", 1, seed=1)
+    _fp32_parity(ctx, L, b, label="B=1")
+    e = gen.workload("dyad_6_20", 1, seed=1).take(np.arange(0))
+    r = ctx.simulate(L.to_device(e), write=L.WRITE_VALID, cap=0)
+    assert int(r["n_written"].cpu()[0]) == 0
+
+
+def test_output_joint_choices(ctx, L):
+    b = gen.workload("dyad_6_20", 3000, seed=12)
+    for out_joint in (0, 1, 2, 5, 19):
+        r = _np(ctx.simulate(L.to_device(b), out_joint=out_joint, write=L.WRITE_ALL, precision=L.FP64,
+                             path_dtype=L.F64))
+        ref = oracle.simulate(b, out_joint=out_joint, path=True, nthreads=NTH)
+        same = (r["path"] == ref["path"]) | (np.isnan(r["path"]) & np.isnan(ref["path"]))
+        assert same.all(), out_joint
+
+
+def test_write_valid_compaction(ctx, L):
+    _say("[compaction]")
+    b = gen.workload("dyad_6_20", 20000, seed=21)
+    db = L.to_device(b)
+    full = _np(ctx.simulate(db, write=L.WRITE_ALL))
+    valid_idx = np.nonzero(full["status"] == 0)[0]
+    for cap in (len(valid_idx) + 10, len(valid_idx), 37, 0):
+        r = _np(ctx.simulate(db, write=L.WRITE_VALID, cap=cap))
+        assert int(r["n_written"][0]) == len(valid_idx)
+        k = min(cap, len(valid_idx))
+        assert np.array_equal(r["path_index"][:k], valid_idx[:k])
+        assert np.array_equal(r["path"][:k], full["path"][valid_idx[:k]])
+
+
+def test_deterministic_across_tunings(ctx, L):
+    _say("[determinism]")
+    b = gen.workload("dyad_skewed", 30000, seed=31)
+    db = L.to_device(b)
+    base = _np(ctx.simulate(db, write=L.WRITE_ALL))
+    try:
+        for w32, rmin, w64 in ((1, 1, 1), (4, 32, 2), (2, 64, 4), (1, 8, 1)):
+            ctx.set_tuning(w32, rmin, w64)
+            r = _np(ctx.simulate(db, write=L.WRITE_ALL))
+            for k in ("status", "fail_step", "esc_step"):
+                assert np.array_equal(r[k], base[k]), (k, w32, rmin, w64)
+            assert np.array_equal(np.nan_to_num(r["path"], nan=7.0), np.nan_to_num(base["path"], nan=7.0))
+    finally:
+        ctx.set_tuning(1, 8, 1)
+    # a candidate gives the same result alone and in the mix
+    for c in (0, 17, 4242):
+        one = _np(ctx.simulate(L.to_device(b.take([c])), write=L.WRITE_ALL))
+        for k in ("status", "fail_step", "esc_step"):
+            assert one[k][0] == base[k][c]
+        assert np.array_equal(np.nan_to_num(one["path"][0], nan=7.0), np.nan_to_num(base["path"][c], nan=7.0))
+
+
+def test_full_size_sampled(ctx, L):
+    """The benchmark's workload and launch (1M dyad-built candidates, n ~ U{6..20},
+    FP32 with escalation, no path output), checked on a sample the oracle computes."""
+    _say("[full size] 1M")
+    b = gen.workload("dyad_6_20", 1_000_000, seed=2)
+    r = _np(ctx.simulate(L.to_device(b), T=200))
+    idx = np.random.default_rng(0).choice(b.B, 40000, replace=False)
+    sb = b.take(idx)
+    ref = oracle.simulate(sb, T=200, margins=True, nthreads=NTH)
+    clear = ~oracle.in_band(ref["margins"])
+    st, fs = r["status"][idx], r["fail_step"][idx]
+    assert np.array_equal(st[clear], ref["status"][clear]) and np.array_equal(fs[clear], ref["fail_step"][clear])
+    assert abs((r["status"] == 0).mean() - (ref["status"] == 0).mean()) < 0.01
+    assert np.all(r["status"] <= 5)
+
+
+def test_normalize_parity(ctx, L):
+    """Both sides normalise the same FP32 paths: coordinates within 1e-5 where
+    neither side raises a flag; flags agree on almost every path (they are
+    threshold decisions); flagged paths agree on the rotation-invariant part
+    (centroid, scale, sorted radii)."""
+    _say("[normalize]")
+    b = gen.workload("dyad_6_20", 20000, seed=41)
+    ref = oracle.simulate(b, path=True, nthreads=NTH)
+    v = ref["status"] == 0
+    paths32 = ref["path"][v].astype(np.float32)
+    for mode in (L.NORM_PCA, L.NORM_DIAMETER):
+        out, xf = ctx.normalize_paths(torch.from_numpy(paths32).cuda(), mode)
+        out, xf = out.cpu().numpy(), xf.cpu().numpy()
+        ro, rxf = oracle.normalize_paths(paths32.astype(np.float64), mode)
+        fo, fg = rxf[:, 4].astype(int), xf[:, 4].astype(int)
+        agree = (fo == fg).mean()
+        plain = (fo == 0) & (fg == 0)
+        assert plain.sum() > 200 and agree > 0.99, (plain.sum(), agree)
+        err = np.abs(out[plain] - ro[plain]).max(axis=(1, 2))
+        _say(f"   mode {mode}: {plain.sum()} unflagged paths, flag agreement {agree:.4f}, max error {err.max():.2e}")
+        assert np.all(err <= 1e-5)
+        flagged = (fo != 0) & (fo == fg) & ((fo & L.NF_CONSTANT) == 0)
+        if mode == L.NORM_PCA and flagged.any():
+            assert np.allclose(xf[flagged, :3], rxf[flagged, :3], rtol=1e-5, atol=1e-6)
+            rg = np.sort(np.hypot(*out[flagged].transpose(2, 0, 1)), axis=1)
+            rr = np.sort(np.hypot(*ro[flagged].transpose(2, 0, 1)), axis=1)
+            assert np.abs(rg - rr).max() <= 1e-5
+
+
+def test_normalize_closed_forms(ctx, L):
+    t = 2 * np.pi * np.arange(200) / 200
+    circle = np.stack([0.3 + 0.1 * np.cos(t), 0.6 + 0.1 * np.sin(t)], -1)
+    seg = np.stack([np.linspace(2, 5, 200), np.linspace(1, -3, 200)], -1)
+    const = np.ones((200, 2))
+    p = torch.from_numpy(np.stack([circle, seg, const]).astype(np.float32)).cuda()
+    out, xf = ctx.normalize_paths(p, L.NORM_PCA)
+    xf = xf.cpu().numpy()
+    assert int(xf[0, 4]) & L.NF_ISOTROPIC and int(xf[2, 4]) == L.NF_CONSTANT
+    out, xf = ctx.normalize_paths(p, L.NORM_DIAMETER)
+    o = out.cpu().numpy()
+    assert np.allclose(o[1, 0], [0, 0.5], atol=1e-6) and np.allclose(o[1, -1], [1, 0.5], atol=1e-6)
+
+
+def test_bad_arguments_raise(ctx, L):
+    b = L.to_device(gen.workload("fourbar", 4))
+    with pytest.raises(L.LinksError):
+        ctx.simulate(b, T=0)
+    with pytest.raises(L.LinksError):
+        ctx.simulate(b, out_joint=99)
+    with pytest.raises(L.LinksError):
+        ctx.normalize_paths(torch.zeros((2, 5000, 2), device="cuda"), L.NORM_PCA)
