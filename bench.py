@@ -3,9 +3,9 @@
 
 One step = the whole hot path over one resident batch of 1,000,000 synthetic
 dyad-built candidates (n ~ U{6..20}, x0 ~ U[0,1)^2, T = 200 actuator positions):
-validation and solve order, bucket sort by solve-order length, the FP32 pass,
-the FP64 hand-over pass, the FP64 path pass, compaction of the valid candidates'
-coupler paths and their PCA normalisation.  Inputs are in HBM before the timed
+validation and solve order, records sorted by solve-order length, the FP32
+decision pass, the FP64 hand-over pass, compaction of the valid candidates, the
+path pass writing their coupler paths and the PCA normalisation of those paths.  Inputs are in HBM before the timed
 region starts.
 
 Printed: one JSON line with the headline throughput (candidates decided per
@@ -67,6 +67,8 @@ def main():
     ap.add_argument("--T", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 leg")
+    ap.add_argument("--handover", choices=["exact", "fast"], default="exact",
+                    help="arithmetic of the FP64 hand-over pass")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
@@ -82,6 +84,7 @@ def main():
     log(f"generated {B} candidates in {time.time() - t0:.1f}s")
     db = L.to_device(host, dev)
     ctx = L.Context(0)
+    ctx.set_option("exact_handover", 1 if args.handover == "exact" else 0)
     out = {"status": torch.empty(B, dtype=torch.uint8, device=dev),
            "fail_step": torch.empty(B, dtype=torch.int16, device=dev),
            "esc_step": torch.empty(B, dtype=torch.int16, device=dev),
@@ -133,7 +136,7 @@ def main():
         "dyad_steps_per_s": float((decided * nd).sum()) / sec32,
         "fp32_pass_ms": pass32["fp32_pass"],
         "fp64_pass_ms": pass32["fp64_pass"],
-        "fp64_path_pass_ms": pass32["fp64_path_pass"],
+        "path_pass_ms": pass32["path_pass"],
         "passes_ms": pass32,
     }
 

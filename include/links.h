@@ -147,7 +147,11 @@ typedef struct {
   int32_t cap;         /* WRITE_VALID: rows available in path / path_index */
 } links_sim_out;
 
-/* Full-rotation simulation of every candidate.  Per step t the tip is turned by
+/* Full-rotation simulation of every candidate.  Decisions (status, fail_step) come
+ * from the FP32 pass and the FP64 hand-over pass (or the FP64 pass alone); the
+ * paths of the selected candidates are then recomputed by a path pass in FP64
+ * (the correctly rounded sequence in FP64 precision, reciprocal square roots with
+ * Newton steps otherwise) and written straight into their rows.  Per step t the tip is turned by
  * theta_t about the pivot, fixed joints stay at x0, and every joint of the solve
  * order is placed at an intersection of the circles about its two parents (radii
  * = initial link lengths).  Of the two intersections the one nearer the joint's
@@ -168,6 +172,15 @@ int links_simulate(links_ctx* ctx, const links_batch* batch, const links_sim_opt
  * the FP32 / FP64 pass (1..4); refill_min = idle lanes a wave waits for before it
  * fetches new candidates (1..64).  Returns LINKS_ERR_ARG outside these ranges. */
 int links_set_tuning(links_ctx* ctx, int waves32, int refill_min, int waves64);
+/* Named integer options (LINKS_ERR_ARG for an unknown name or value):
+ *   "waves32", "refill_min", "waves64"  as in links_set_tuning;
+ *   "refill64"        idle lanes a wave of the FP64 passes waits for before it
+ *                     fetches new candidates (1..64, default 32);
+ *   "exact_handover"  1 (default): the FP64 hand-over pass evaluates the correctly
+ *                     rounded sequence of the FP64 precision; 0: reciprocal square
+ *                     roots refined by Newton steps (relative error ~1e-15). */
+int links_set_option(links_ctx* ctx, const char* name, int value);
+
 /* Current launch parameters and the persistent grid sizes of the last call (any
  * pointer may be NULL). */
 int links_get_tuning(links_ctx* ctx, int* waves32, int* refill_min, int* waves64, int* grid32, int* grid64);
@@ -191,8 +204,10 @@ int links_normalize_paths_n(links_ctx* ctx, const float* paths, const int32_t* c
 /* Kernel timing.  With profiling enabled the next links_simulate records HIP
  * events around each of its passes on the call's stream; links_last_timings
  * synchronises with the last recorded event and writes the elapsed milliseconds
- * of up to n passes, in this order: prep, bucket sort, FP32 pass, FP64 hand-over
- * pass (or the FP64 pass in FP64 precision), FP64 path pass, compaction.  A pass
+ * of up to n passes, in this order: set-up count (validation, solve-order length,
+ * bucket offsets), set-up fill (solve order and records at the sorted position),
+ * FP32 pass, FP64 pass (hand-over list, or every candidate in FP64 precision),
+ * compaction and path selection, path pass.  A pass
  * that did not run reports 0.  Returns the number of values written. */
 #define LINKS_TIMING_PASSES 6
 int links_profile(links_ctx* ctx, int enable);

@@ -32,13 +32,17 @@ TAU_DRIFT = 1e-4
 
 _lib = None
 
+# every operation as written: no fused multiply-adds, no fast-math, and cos / sin
+# called as such (not merged into one sincos call by the compiler)
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fno-builtin-sin", "-fno-builtin-cos",
+          "-fno-builtin-sincos", "-fPIC", "-shared"]
+
 
 def build(force: bool = True) -> str:
     """Compile the oracle library with gcc (always, when ``force``)."""
     if force or not os.path.exists(LIB):
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-                               "-Wall", "-o", tmp, SRC, "-lm", "-lpthread"])
+        subprocess.check_call(["gcc", *CFLAGS, "-Wall", "-o", tmp, SRC, "-lm", "-lpthread"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -48,8 +52,7 @@ def build_variant(src_text: str, out_path: str) -> str:
     src = out_path + ".c"
     with open(src, "w") as f:
         f.write(src_text)
-    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-I", HERE,
-                           "-o", out_path, src, "-lm", "-lpthread"])
+    subprocess.check_call(["gcc", *CFLAGS, "-I", HERE, "-o", out_path, src, "-lm", "-lpthread"])
     return out_path
 
 

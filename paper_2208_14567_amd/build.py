@@ -21,6 +21,8 @@ FLAGS = [
     "-ffp-contract=off",
     # packed FP32 instructions are not generated
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the host-side crank table calls cos and sin as written (no merged sincos)
+    "-fno-builtin-sin", "-fno-builtin-cos", "-fno-builtin-sincos",
     "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
     "-I", os.path.join(ROOT, "include"),
 ]

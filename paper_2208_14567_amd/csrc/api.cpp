@@ -50,8 +50,10 @@ struct links_ctx {
   std::vector<float> cs32_host;
   // launch parameters (see links_set_tuning)
   int waves32 = 1;
-  int refill_min = 8;
+  int refill_min = 48;
   int waves64 = 1;
+  int refill64 = 32;           // refill threshold of the FP64 passes
+  bool exact_handover = true;  // FP64 hand-over pass with the correctly rounded sequence
   std::map<std::string, int> occ_cache;
   // last call's statistics
   int last_grid32 = 0, last_grid64 = 0;
@@ -212,6 +214,25 @@ int links_set_tuning(links_ctx* ctx, int waves32, int refill_min, int waves64) {
   return LINKS_OK;
 }
 
+int links_set_option(links_ctx* ctx, const char* name, int value) {
+  if (!ctx || !name) return fail(LINKS_ERR_ARG, "NULL argument");
+  const std::string k(name);
+  if (k == "waves32") return links_set_tuning(ctx, value, ctx->refill_min, ctx->waves64);
+  if (k == "refill_min") return links_set_tuning(ctx, ctx->waves32, value, ctx->waves64);
+  if (k == "waves64") return links_set_tuning(ctx, ctx->waves32, ctx->refill_min, value);
+  if (k == "refill64") {
+    if (value < 1 || value > 64) return fail(LINKS_ERR_ARG, "refill64 must be in 1..64");
+    ctx->refill64 = value;
+    return LINKS_OK;
+  }
+  if (k == "exact_handover") {
+    if (value != 0 && value != 1) return fail(LINKS_ERR_ARG, "exact_handover must be 0 or 1");
+    ctx->exact_handover = value != 0;
+    return LINKS_OK;
+  }
+  return fail(LINKS_ERR_ARG, "unknown option '%s'", name);
+}
+
 int links_get_tuning(links_ctx* ctx, int* waves32, int* refill_min, int* waves64, int* grid32, int* grid64) {
   if (!ctx) return fail(LINKS_ERR_ARG, "ctx is NULL");
   if (waves32) *waves32 = ctx->waves32;
@@ -245,7 +266,7 @@ int links_solve_order(links_ctx* ctx, const links_batch* batch, int8_t* order, u
   a.depth = depth;
   a.status = status;
   a.sim = 0;
-  HIP_CHECK(links::launch_prep(a, (hipStream_t)stream));
+  HIP_CHECK(links::launch_solve_order(a, (hipStream_t)stream));
   return LINKS_OK;
 }
 
@@ -261,14 +282,15 @@ int links_simulate(links_ctx* ctx, const links_batch* batch, const links_sim_opt
   if (opts->write < 0 || opts->write > 2) return fail(LINKS_ERR_ARG, "bad write mode %d", opts->write);
   if (opts->path_dtype != LINKS_F32 && opts->path_dtype != LINKS_F64)
     return fail(LINKS_ERR_ARG, "bad path dtype %d", opts->path_dtype);
-  if (opts->out_joint < -1 || opts->out_joint >= J) return fail(LINKS_ERR_ARG, "out_joint %d outside [-1, J)", opts->out_joint);
+  if (opts->out_joint < -1 || opts->out_joint >= J)
+    return fail(LINKS_ERR_ARG, "out_joint %d outside [-1, J)", opts->out_joint);
   if (!(opts->eps_disc >= 0) || !(opts->eps_branch >= 0) || !(opts->tau_drift >= 0))
     return fail(LINKS_ERR_ARG, "negative or NaN tolerance");
   if (B > 0 && (!batch->x0 || !out->status)) return fail(LINKS_ERR_ARG, "x0 or status is NULL");
-  if (opts->write != LINKS_WRITE_NONE && B > 0 && !out->path && !(opts->write == LINKS_WRITE_VALID && out->cap == 0))
-    return fail(LINKS_ERR_ARG, "path is NULL");
-  if (opts->write == LINKS_WRITE_VALID && (out->cap < 0 || !out->n_written || (out->cap > 0 && !out->path_index)))
-    return fail(LINKS_ERR_ARG, "WRITE_VALID needs cap >= 0, n_written and path_index");
+  if (opts->write == LINKS_WRITE_ALL && B > 0 && !out->path) return fail(LINKS_ERR_ARG, "path is NULL");
+  if (opts->write == LINKS_WRITE_VALID &&
+      (out->cap < 0 || !out->n_written || (out->cap > 0 && (!out->path_index || !out->path))))
+    return fail(LINKS_ERR_ARG, "WRITE_VALID needs cap >= 0, n_written, and path and path_index when cap > 0");
   rc = set_device(ctx);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
@@ -290,28 +312,32 @@ int links_simulate(links_ctx* ctx, const links_batch* batch, const links_sim_opt
   EscEntry* esc;
   float2* esc_pos;
   int16_t* fail_ws;
-  int32_t* refine;
-  if ((rc = ensure_t(ctx, "refine", B, &refine))) return rc;
+  int32_t* path_list;
+  int32_t* path_row;
+  uint8_t* dlen;
+  int32_t* block_hist;
+  int32_t* block_off;
+  int32_t* scratch;
+  const size_t nblocks = (size_t)prep_blocks(B);
   if ((rc = ensure_t(ctx, "meta", B, &meta)) || (rc = ensure_t(ctx, "cf", B, &cf)) ||
       (rc = ensure_t(ctx, "cd", B, &cd)) || (rc = ensure_t(ctx, "df", (size_t)B * J, &df)) ||
       (rc = ensure_t(ctx, "dd", (size_t)B * J, &dd)) || (rc = ensure_t(ctx, "x0s", (size_t)B * J, &x0s)) ||
       (rc = ensure_t(ctx, "sj", (size_t)B * J, &sj)) || (rc = ensure_t(ctx, "perm", B, &perm)) ||
       (rc = ensure_t(ctx, "counters", kCntSize, &counters)) || (rc = ensure_t(ctx, "esc", B, &esc)) ||
-      (rc = ensure_t(ctx, "esc_pos", (size_t)B * J, &esc_pos)) || (rc = ensure_t(ctx, "fail_ws", B, &fail_ws)))
+      (rc = ensure_t(ctx, "esc_pos", (size_t)B * J, &esc_pos)) || (rc = ensure_t(ctx, "fail_ws", B, &fail_ws)) ||
+      (rc = ensure_t(ctx, "path_list", B, &path_list)) || (rc = ensure_t(ctx, "path_row", B, &path_row)) ||
+      (rc = ensure_t(ctx, "dlen", B, &dlen)) ||
+      (rc = ensure_t(ctx, "block_hist", nblocks * kMaxJ, &block_hist)) ||
+      (rc = ensure_t(ctx, "block_off", nblocks * kMaxJ, &block_off)) ||
+      (rc = ensure_t(ctx, "compact", compact_scratch_ints(B), &scratch)))
     return rc;
   float2* cs32;
   double2* cs64;
   if ((rc = crank_table(ctx, T, st, &cs32, &cs64))) return rc;
 
   const size_t elt = opts->path_dtype == LINKS_F64 ? sizeof(double2) : sizeof(float2);
-  void* path = nullptr;
-  if (opts->write == LINKS_WRITE_ALL) {
-    path = out->path;
-    HIP_CHECK(launch_fill_u32(path, (size_t)B * T * elt / 4, 0xFFFFFFFFu, st));  // NaN
-  } else if (opts->write == LINKS_WRITE_VALID) {
-    if ((rc = ensure(ctx, "staging", (size_t)B * T * elt, &path))) return rc;
-  }
-
+  if (opts->write == LINKS_WRITE_ALL)
+    HIP_CHECK(launch_fill_u32(out->path, (size_t)B * T * elt / 4, 0xFFFFFFFFu, st));  // NaN rows
   HIP_CHECK(launch_fill_u32(counters, kCntSize, 0u, st));
   int16_t* fail_step = out->fail_step ? out->fail_step : fail_ws;
 
@@ -330,7 +356,6 @@ int links_simulate(links_ctx* ctx, const links_batch* batch, const links_sim_opt
   pa.eps_disc = opts->eps_disc;
   pa.eps_branch = opts->eps_branch;
   pa.tau_drift = opts->tau_drift;
-  pa.path_tol = 1e-5;
   pa.fail_step = fail_step;
   pa.esc_step = out->esc_step;
   pa.meta = meta;
@@ -341,13 +366,21 @@ int links_simulate(links_ctx* ctx, const links_batch* batch, const links_sim_opt
   pa.x0s = x0s;
   pa.slot_joint = sj;
   pa.counters = counters;
+  pa.Bs = B;
+  pa.dlen = dlen;
+  pa.block_hist = block_hist;
+  pa.block_off = block_off;
+  pa.perm = perm;
   for (int i = 0; i < LINKS_TIMING_PASSES; i++) ctx->ev_used[i] = false;
   ctx->ev_ready = false;
+  // set-up: validation and solve-order length, bucket offsets, then the records
+  // written at each candidate's sorted position (largest solve order first)
   if ((rc = mark(ctx, 0, st))) return rc;
-  HIP_CHECK(launch_prep(pa, st));
+  HIP_CHECK(launch_prep_count(pa, st));
+  HIP_CHECK(launch_prep_offsets(pa, st));
   ctx->ev_used[0] = true;
   if ((rc = mark(ctx, 1, st))) return rc;
-  HIP_CHECK(launch_bucket_sort(B, out->status, meta, counters, perm, st));
+  HIP_CHECK(launch_prep_fill(pa, st));
   ctx->ev_used[1] = true;
   if ((rc = mark(ctx, 2, st))) return rc;
 
@@ -356,6 +389,7 @@ int links_simulate(links_ctx* ctx, const links_batch* batch, const links_sim_opt
   sa.B = B;
   sa.J = J;
   sa.T = T;
+  sa.Bs = B;
   sa.n = batch->n;
   sa.adj = batch->adj;
   sa.fixed = batch->fixed;
@@ -372,14 +406,15 @@ int links_simulate(links_ctx* ctx, const links_batch* batch, const links_sim_opt
   sa.counters = counters;
   sa.esc = esc;
   sa.esc_pos = esc_pos;
-  sa.refine = refine;
+  sa.path_list = path_list;
+  sa.path_row = path_row;
   sa.write_all = opts->write == LINKS_WRITE_ALL;
   sa.cs32 = cs32;
   sa.cs64 = cs64;
   sa.status = out->status;
   sa.fail_step = fail_step;
   sa.esc_step = out->esc_step;
-  sa.path = path;
+  sa.path = out->path;
   sa.path_f64 = opts->path_dtype == LINKS_F64;
   sa.nslot = J;
   sa.refill_min = ctx->refill_min;
@@ -388,43 +423,51 @@ int links_simulate(links_ctx* ctx, const links_batch* batch, const links_sim_opt
   c64.waves = ctx->waves64;
   c64.refill_min = 1;
   const int lds64 = sim64_lds_bytes(J, c64.waves);
-  const int source = opts->precision == LINKS_FP64 ? kFromPerm : kFromEsc;
-  c64.grid = grid_for(ctx, "sim64", sim64_blocks_per_cu(J, source, c64.waves, lds64));
-  if (opts->precision == LINKS_FP64) {
+  const bool fp64 = opts->precision == LINKS_FP64;
+  // ---- decisions
+  SimArgs sa64 = sa;
+  sa64.refill_min = ctx->refill64;
+  if (fp64) {
+    c64.grid = grid_for(ctx, "sim64", sim64_blocks_per_cu(J, kFromPerm, true, c64.waves, lds64));
     if ((rc = mark(ctx, 3, st))) return rc;
-    HIP_CHECK(launch_sim64(sa, kFromPerm, c64, st));
+    HIP_CHECK(launch_sim64(sa64, kFromPerm, true, c64, st));
     ctx->ev_used[3] = true;
-    if ((rc = mark(ctx, 4, st))) return rc;
     ctx->last_grid32 = 0;
   } else {
     LaunchCfg c32;
     c32.waves = ctx->waves32;
     c32.refill_min = ctx->refill_min;
     const int mode = opts->precision == LINKS_FP32_ONLY ? 1 : 0;
-    const int lds32 = sim32_lds_bytes(J, c32.waves);
-    c32.grid = grid_for(ctx, "sim32", sim32_blocks_per_cu(J, mode, c32.waves, lds32));
+    const int lds32 = sim32_lds_bytes(J, c32.waves, T);
+    c32.grid = grid_for(ctx, "sim32", sim32_blocks_per_cu(J, mode, T, c32.waves, lds32));
     HIP_CHECK(launch_sim32(sa, mode, c32, st));
     ctx->ev_used[2] = true;
+    c64.grid = grid_for(ctx, "sim64", sim64_blocks_per_cu(J, kFromEsc, ctx->exact_handover, c64.waves, lds64));
     if ((rc = mark(ctx, 3, st))) return rc;
-    HIP_CHECK(launch_sim64(sa, kFromEsc, c64, st));
+    HIP_CHECK(launch_sim64(sa64, kFromEsc, ctx->exact_handover, c64, st));
     ctx->ev_used[3] = true;
-    if ((rc = mark(ctx, 4, st))) return rc;
-    if (path != nullptr && mode == 0) {
-      HIP_CHECK(launch_sim64(sa, kFromRefine, c64, st));
-      ctx->ev_used[4] = true;
-    }
     ctx->last_grid32 = c32.grid;
   }
   ctx->last_grid64 = c64.grid;
-
-  if ((rc = mark(ctx, 5, st))) return rc;
+  // ---- compaction of the valid candidates and the list of paths to write
+  if ((rc = mark(ctx, 4, st))) return rc;
   if (opts->write == LINKS_WRITE_VALID) {
-    ctx->ev_used[5] = true;
-    int32_t* scratch;
-    if ((rc = ensure_t(ctx, "compact", compact_scratch_ints(B), &scratch))) return rc;
-    HIP_CHECK(launch_compact(B, out->status, scratch, out->path_index, out->cap, out->n_written, st));
+    HIP_CHECK(launch_compact(B, out->status, scratch, out->path_index, out->cap, out->n_written, path_row, st));
     if (out->cap > 0)
-      HIP_CHECK(launch_gather_rows(out->path_index, out->n_written, out->cap, path, out->path, (size_t)T * elt, st));
+      HIP_CHECK(launch_select_paths(B, perm, out->status, path_row, 0, scratch, path_list, counters, st));
+    ctx->ev_used[4] = true;
+  } else if (opts->write == LINKS_WRITE_ALL) {
+    HIP_CHECK(launch_select_paths(B, perm, out->status, path_row, 1, scratch, path_list, counters, st));
+    ctx->ev_used[4] = true;
+  }
+  // ---- path pass: the output joint of every selected candidate, step by step,
+  // written straight into its output row
+  if ((rc = mark(ctx, 5, st))) return rc;
+  if (opts->write != LINKS_WRITE_NONE && !(opts->write == LINKS_WRITE_VALID && out->cap == 0)) {
+    LaunchCfg cp = c64;
+    cp.grid = grid_for(ctx, "path", sim64_blocks_per_cu(J, kFromPath, fp64, cp.waves, lds64));
+    HIP_CHECK(launch_sim64(sa64, kFromPath, fp64, cp, st));
+    ctx->ev_used[5] = true;
   }
   if ((rc = mark(ctx, 6, st))) return rc;
   ctx->ev_ready = ctx->profile;

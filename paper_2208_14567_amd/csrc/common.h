@@ -35,12 +35,11 @@ struct CandF32 {
   float KB;      // escalation band on K: 4 eps_disc scale^4
   float CD;      // escalation band on d^2: eps_disc scale^2
   float EB;      // escalation band on the branch distance: eps_branch scale
-  float EP;      // largest tolerated path error: path_tol scale
   float U2;      // rounding of one placement relative to the link lengths: u 2 scale
   float TS;      // 2 scale, a bound on 2 ra in the branch error term
   float u;       // relative rounding unit of a placement
   float DG;      // degenerate threshold 1e-12 scale^2 (FP32-only mode)
-  float pad[3];
+  float pad[4];
 };
 
 // FP64 constants of one candidate
@@ -67,10 +66,10 @@ struct DyadF64 {
 
 // A candidate handed from the FP32 pass to the FP64 pass.
 struct EscEntry {
-  int32_t cand;
+  int32_t item;   // sorted position of the candidate (its records)
   int16_t t;      // step to recompute in FP64
   int8_t from_x0;    // 1: start from x0 at step 0 (links outside the solve order)
-  int8_t path_bad;   // 1: the FP32 steps before t exceeded the path error bound
+  int8_t pad;
 };
 
 // Pointers of the workspace and of the caller's batch, passed by value to kernels.
@@ -82,20 +81,23 @@ struct SimArgs {
   const uint32_t* fixed;
   const uint8_t* motor;
   const double* x0;
-  // records
+  // records, stored at the sorted position p: per candidate [p], per entry or
+  // slot [s * Bs + p]
+  int32_t Bs;
   CandMeta* meta;
   CandF32* cf;
   CandF64* cd;
-  DyadF32* df;      // [B][J]
-  DyadF64* dd;      // [B][J]
-  float2* x0s;      // [B][J] initial positions in slot order (FP32)
-  uint8_t* slot_joint;  // [B][J] joint in each slot
+  DyadF32* df;      // [J][Bs]
+  DyadF64* dd;      // [J][Bs]
+  float2* x0s;      // [J][Bs] initial positions in slot order (FP32)
+  uint8_t* slot_joint;  // [J][Bs] joint in each slot
   // scheduling
-  int32_t* perm;    // [B] candidates to simulate, largest D first
+  int32_t* perm;    // [B] candidate at each sorted position (largest D first)
   int32_t* counters;  // [0] next work item, [1] work items, [2] escalations, [3] next esc item, [4..] D histogram
   EscEntry* esc;    // [B]
-  int32_t* refine;  // [B] candidates whose path is recomputed in FP64
-  int32_t write_all;  // every candidate's path is output (else only valid ones)
+  int32_t* path_list;  // [B] sorted positions of the candidates whose path is written
+  int32_t* path_row;   // [B] output row of each valid candidate (WRITE_VALID), -1 beyond cap
+  int32_t write_all;   // every simulated candidate's path is output (row = candidate)
   float2* esc_pos;  // [B][J] FP32 slot positions at hand-over
   // crank table
   const float2* cs32;   // [T] (cos, sin) rounded from FP64

@@ -10,11 +10,12 @@ constexpr int kCntItems = 1;    // work items of the simulation pass
 constexpr int kCntEsc = 2;      // candidates handed to FP64
 constexpr int kCntEscNext = 3;  // next hand-over item taken by the FP64 pass
 constexpr int kCntValid = 4;    // valid candidates (compaction)
-constexpr int kCntRefine = 5;   // candidates whose FP32 path must be recomputed in FP64
-constexpr int kCntRefineNext = 6;
+constexpr int kCntPath = 5;     // candidates whose path is written
+constexpr int kCntPathNext = 6;
 constexpr int kCntHist = 8;     // [32] histogram of solve-order lengths
 constexpr int kCntOff = 40;     // [32] bucket offsets
-constexpr int kCntSize = 72;
+constexpr int kCntCur = 72;     // [32] next item of each bucket (FP32 pass)
+constexpr int kCntSize = 104;
 
 struct PrepArgs {
   int32_t B, J;
@@ -31,7 +32,7 @@ struct PrepArgs {
   // simulation records (sim != 0)
   int32_t sim;
   int32_t out_joint;
-  double eps_disc, eps_branch, tau_drift, path_tol;
+  double eps_disc, eps_branch, tau_drift;
   int16_t* fail_step;
   int16_t* esc_step;
   CandMeta* meta;
@@ -42,17 +43,28 @@ struct PrepArgs {
   float2* x0s;
   uint8_t* slot_joint;
   int32_t* counters;
+  // sorting by solve-order length (records are written at the sorted position)
+  int32_t Bs;            // stride of the per-entry record arrays
+  uint8_t* dlen;         // [B] solve-order length, 0xFF when not simulated
+  int32_t* block_hist;   // [blocks][32]
+  int32_t* block_off;    // [blocks][32]
+  int32_t* perm;         // [B] candidate at each sorted position
 };
 
-hipError_t launch_prep(const PrepArgs& a, hipStream_t st);
-hipError_t launch_bucket_sort(int32_t B, const uint8_t* status, const CandMeta* meta, int32_t* counters,
-                              int32_t* perm, hipStream_t st);
+hipError_t launch_solve_order(const PrepArgs& a, hipStream_t st);
+int prep_blocks(int32_t B);
+hipError_t launch_prep_count(const PrepArgs& a, hipStream_t st);
+hipError_t launch_prep_offsets(const PrepArgs& a, hipStream_t st);
+hipError_t launch_prep_fill(const PrepArgs& a, hipStream_t st);
 hipError_t launch_fill_u32(void* p, size_t n_u32, uint32_t v, hipStream_t st);
 size_t compact_scratch_ints(int32_t B);
 hipError_t launch_compact(int32_t B, const uint8_t* status, int32_t* scratch, int32_t* index, int32_t cap,
-                          int32_t* total, hipStream_t st);
-hipError_t launch_gather_rows(const int32_t* index, const int32_t* total, int32_t cap, const void* staged,
-                              void* out, size_t row_bytes, hipStream_t st);
+                          int32_t* total, int32_t* row_of, hipStream_t st);
+// path list over sorted positions: valid candidates with a row (all_simulated = 0)
+// or every simulated candidate (1); count in counters[kCntPath]
+hipError_t launch_select_paths(int32_t B, const int32_t* perm, const uint8_t* status, const int32_t* row_of,
+                               int all_simulated, int32_t* scratch, int32_t* list, int32_t* counters,
+                               hipStream_t st);
 
 // Simulation passes.  `grid` = persistent workgroups; block = waves * 64 lanes.
 struct LaunchCfg {
@@ -62,17 +74,20 @@ struct LaunchCfg {
 };
 // FP32 pass: mode 0 escalates to FP64, mode 1 never escalates.
 hipError_t launch_sim32(const SimArgs& a, int mode, const LaunchCfg& cfg, hipStream_t st);
-int sim32_lds_bytes(int nslot, int waves);
+int sim32_lds_bytes(int nslot, int waves, int T);
+constexpr int kTableLds = 1024;  // crank tables up to this many steps live in LDS
 int sim32_dmax(int J);
 // FP64 pass work sources
 constexpr int kFromPerm = 0;    // every pending candidate from t = 0 (plain FP64 precision)
 constexpr int kFromEsc = 1;     // candidates handed over by the FP32 pass, from their step
-constexpr int kFromRefine = 2;  // candidates whose FP32 path exceeded its error bound, from t = 0
-hipError_t launch_sim64(const SimArgs& a, int source, const LaunchCfg& cfg, hipStream_t st);
+constexpr int kFromPath = 2;    // path pass: candidates whose path is output, from t = 0
+// exact: the correctly rounded IEEE sequence (else reciprocal square roots refined
+// by Newton steps)
+hipError_t launch_sim64(const SimArgs& a, int source, bool exact, const LaunchCfg& cfg, hipStream_t st);
 int sim64_lds_bytes(int nslot, int waves);
 // occupancy helper: resident workgroups per CU for a kernel variant
-int sim32_blocks_per_cu(int J, int mode, int waves, int lds_bytes);
-int sim64_blocks_per_cu(int J, int source, int waves, int lds_bytes);
+int sim32_blocks_per_cu(int J, int mode, int T, int waves, int lds_bytes);
+int sim64_blocks_per_cu(int J, int source, bool exact, int waves, int lds_bytes);
 
 // Path normalisation, one wave per path.
 hipError_t launch_normalize(const float* paths, int32_t P, const int32_t* count, int32_t T, int32_t mode,

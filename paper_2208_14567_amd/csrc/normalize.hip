@@ -1,4 +1,5 @@
-// normalize.hip -- path normalisation, one wave (64 lanes) per path, FP32.
+// normalize.hip -- path normalisation, one wave (64 lanes) per path; FP32 paths in
+// and out, moments and rotations evaluated in FP64.
 //
 // DIAMETER mode is the paper's rule (Methodology, "Dataset Curation &
 // Processing"): find the longest chord of the path, turn it onto +x, scale it to
@@ -33,6 +34,21 @@ __device__ __forceinline__ float wmax(float v) {
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
   return v;
 }
+__device__ __forceinline__ double wsumd(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ double wmind(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ double wmaxd(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
 __device__ __forceinline__ int wsumi(int v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -52,70 +68,70 @@ __global__ void __launch_bounds__(kNormWaves * kWave) normalize_kernel(const flo
     const float2* src = reinterpret_cast<const float2*>(paths) + (size_t)p * T;
     float2* dst = reinterpret_cast<float2*>(out) + (size_t)p * T;
     const float2 p0 = src[0];
-    for (int i = lane; i < T; i += kWave) {
-      const float2 q = src[i];
-      pts[i] = make_float2(q.x - p0.x, q.y - p0.y);
-    }
+    for (int i = lane; i < T; i += kWave) pts[i] = src[i];
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    // coordinates relative to the first point, exact in FP64
+    const double ox = p0.x, oy = p0.y;
+    auto X = [&](int i) { return (double)pts[i].x - ox; };
+    auto Y = [&](int i) { return (double)pts[i].y - oy; };
     float xf[5];
     if (mode == 0) {
-      // ---- centroid, RMS radius, principal axis
-      float sx = 0.f, sy = 0.f;
+      // ---- centroid, RMS radius, principal axis (moments accumulated in FP64: the
+      // axis angle is ill-conditioned when the two eigenvalues are close)
+      double sx = 0.0, sy = 0.0;
       for (int i = lane; i < T; i += kWave) {
-        sx += pts[i].x;
-        sy += pts[i].y;
+        sx += X(i);
+        sy += Y(i);
       }
-      const float mx = wsum(sx) / T, my = wsum(sy) / T;
-      float ss = 0.f;
+      const double mx = wsumd(sx) / T, my = wsumd(sy) / T;
+      double ss = 0.0;
       for (int i = lane; i < T; i += kWave) {
-        const float qx = pts[i].x - mx, qy = pts[i].y - my;
-        ss = fmaf(qx, qx, fmaf(qy, qy, ss));
+        const double qx = X(i) - mx, qy = Y(i) - my;
+        ss += qx * qx + qy * qy;
       }
-      const float s = sqrtf(wsum(ss) / T);
-      const float cx = p0.x + mx, cy = p0.y + my;
-      if (!(s >= 1e-12f)) {
+      const double s = sqrt(wsumd(ss) / T);
+      const double cx = ox + mx, cy = oy + my;
+      if (!(s >= 1e-12)) {
         for (int i = lane; i < T; i += kWave) dst[i] = make_float2(0.f, 0.f);
-        xf[0] = cx; xf[1] = cy; xf[2] = 0.f; xf[3] = 0.f; xf[4] = 1.f;
+        xf[0] = (float)cx; xf[1] = (float)cy; xf[2] = 0.f; xf[3] = 0.f; xf[4] = 1.f;
       } else {
-        const float is = 1.f / s;
-        float axx = 0.f, axy = 0.f, ayy = 0.f;
+        double axx = 0.0, axy = 0.0, ayy = 0.0;
         for (int i = lane; i < T; i += kWave) {
-          const float qx = (pts[i].x - mx) * is, qy = (pts[i].y - my) * is;
-          axx = fmaf(qx, qx, axx);
-          axy = fmaf(qx, qy, axy);
-          ayy = fmaf(qy, qy, ayy);
+          const double qx = (X(i) - mx) / s, qy = (Y(i) - my) / s;
+          axx += qx * qx;
+          axy += qx * qy;
+          ayy += qy * qy;
         }
-        const float cxx = wsum(axx) / T, cxy = wsum(axy) / T, cyy = wsum(ayy) / T;
-        const float dxy = cxx - cyy;
-        const float gap = sqrtf(fmaf(dxy, dxy, 4.f * cxy * cxy));
+        const double cxx = wsumd(axx) / T, cxy = wsumd(axy) / T, cyy = wsumd(ayy) / T;
+        const double dxy = cxx - cyy;
+        const double gap = sqrt(dxy * dxy + 4.0 * cxy * cxy);
         int flags = 0;
-        float phi = 0.5f * atan2f(2.f * cxy, dxy);
-        if (gap < 1e-4f * (cxx + cyy)) {
-          phi = 0.f;
+        double phi = 0.5 * atan2(2.0 * cxy, dxy);
+        if (gap < 1e-4 * (cxx + cyy)) {
+          phi = 0.0;
           flags |= 2;
         }
-        float sn, c;
-        sincosf(phi, &sn, &c);
-        float m3 = 0.f;
+        const double c = cos(phi), sn = sin(phi);
+        double m3 = 0.0;
         for (int i = lane; i < T; i += kWave) {
-          const float qx = (pts[i].x - mx) * is, qy = (pts[i].y - my) * is;
-          const float rx = fmaf(c, qx, sn * qy);
-          m3 = fmaf(rx * rx, rx, m3);
+          const double qx = (X(i) - mx) / s, qy = (Y(i) - my) / s;
+          const double rx = c * qx + sn * qy;
+          m3 += rx * rx * rx;
         }
-        m3 = wsum(m3);
-        float sign = 1.f;
-        if (fabsf(m3) < 1e-6f * T) {
+        m3 = wsumd(m3);
+        double sign = 1.0;
+        if (fabs(m3) < 1e-6 * T) {
           flags |= 4;
-        } else if (m3 < 0.f) {
-          sign = -1.f;
-          phi += 3.14159265358979323846f;
+        } else if (m3 < 0.0) {
+          sign = -1.0;
+          phi += 3.14159265358979323846;
         }
         for (int i = lane; i < T; i += kWave) {
-          const float qx = (pts[i].x - mx) * is, qy = (pts[i].y - my) * is;
-          dst[i] = make_float2(sign * fmaf(c, qx, sn * qy), sign * fmaf(-sn, qx, c * qy));
+          const double qx = (X(i) - mx) / s, qy = (Y(i) - my) / s;
+          dst[i] = make_float2((float)(sign * (c * qx + sn * qy)), (float)(sign * (-sn * qx + c * qy)));
         }
-        xf[0] = cx; xf[1] = cy; xf[2] = s; xf[3] = phi; xf[4] = (float)flags;
+        xf[0] = (float)cx; xf[1] = (float)cy; xf[2] = (float)s; xf[3] = (float)phi; xf[4] = (float)flags;
       }
     } else {
       // ---- longest chord: first pair (i < j) in lexicographic order
@@ -158,30 +174,28 @@ __global__ void __launch_bounds__(kNormWaves * kWave) normalize_kernel(const flo
           }
         }
         if (wsumi(ties) > 0) flags |= 8;
-        const float Dl = sqrtf(best);
-        const float ux = pts[bj].x - pts[bi].x, uy = pts[bj].y - pts[bi].y;
-        const float phi = atan2f(uy, ux);
-        float sn, c;
-        sincosf(phi, &sn, &c);
-        const float iD = 1.f / Dl;
-        const float ax = pts[bi].x, ay = pts[bi].y;
-        float xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
+        const double ax = X(bi), ay = Y(bi);
+        const double ux = X(bj) - ax, uy = Y(bj) - ay;
+        const double Dl = sqrt(ux * ux + uy * uy);
+        const double phi = atan2(uy, ux);
+        const double c = cos(phi), sn = sin(phi);
+        double xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
         for (int i = lane; i < T; i += kWave) {
-          const float qx = pts[i].x - ax, qy = pts[i].y - ay;
-          const float rx = fmaf(c, qx, sn * qy) * iD, ry = fmaf(-sn, qx, c * qy) * iD;
-          xmin = fminf(xmin, rx); xmax = fmaxf(xmax, rx);
-          ymin = fminf(ymin, ry); ymax = fmaxf(ymax, ry);
+          const double qx = X(i) - ax, qy = Y(i) - ay;
+          const double rx = (c * qx + sn * qy) / Dl, ry = (-sn * qx + c * qy) / Dl;
+          xmin = fmin(xmin, rx); xmax = fmax(xmax, rx);
+          ymin = fmin(ymin, ry); ymax = fmax(ymax, ry);
         }
-        xmin = wmin(xmin); xmax = wmax(xmax); ymin = wmin(ymin); ymax = wmax(ymax);
-        const float mx = 0.5f * (xmin + xmax), my = 0.5f * (ymin + ymax);
+        xmin = wmind(xmin); xmax = wmaxd(xmax); ymin = wmind(ymin); ymax = wmaxd(ymax);
+        const double mx = 0.5 * (xmin + xmax), my = 0.5 * (ymin + ymax);
         for (int i = lane; i < T; i += kWave) {
-          const float qx = pts[i].x - ax, qy = pts[i].y - ay;
-          const float rx = fmaf(c, qx, sn * qy) * iD, ry = fmaf(-sn, qx, c * qy) * iD;
-          dst[i] = make_float2(rx - mx + 0.5f, ry - my + 0.5f);
+          const double qx = X(i) - ax, qy = Y(i) - ay;
+          const double rx = (c * qx + sn * qy) / Dl, ry = (-sn * qx + c * qy) / Dl;
+          dst[i] = make_float2((float)(rx - mx + 0.5), (float)(ry - my + 0.5));
         }
-        xf[0] = p0.x + ax + Dl * (c * mx - sn * my);
-        xf[1] = p0.y + ay + Dl * (sn * mx + c * my);
-        xf[2] = Dl; xf[3] = phi; xf[4] = (float)flags;
+        xf[0] = (float)(ox + ax + Dl * (c * mx - sn * my));
+        xf[1] = (float)(oy + ay + Dl * (sn * mx + c * my));
+        xf[2] = (float)Dl; xf[3] = (float)phi; xf[4] = (float)flags;
       }
     }
     if (lane < 5) {

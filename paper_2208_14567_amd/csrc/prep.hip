@@ -25,11 +25,85 @@ __device__ inline double sqd(const double* p, const double* q) {
   return dx * dx + dy * dy;
 }
 
-constexpr int kPrepBlock = 128;
+constexpr int kPrepBlock = 128;   // solve-order kernel
+constexpr int kSortBlock = 256;   // count and fill kernels (same blocking)
 
-__global__ void __launch_bounds__(kPrepBlock) prep_kernel(PrepArgs A) {
-  __shared__ uint32_t ord_l[kMaxJ][kPrepBlock];  // (k | a << 8 | b << 16) per entry
-  __shared__ uint8_t idx_l[kMaxJ][kPrepBlock];   // solve-order index of each placed joint
+// Integer structure of one candidate (the rules links_solve_order documents).
+__device__ bool structure_ok(int J, int n, const uint32_t* adj, uint32_t fixed, int pivot, int tip) {
+  if (n < 3 || n > J) return false;
+  const uint32_t live = live_mask(n);
+  if (fixed & ~live) return false;
+  for (int i = 0; i < J; i++) {
+    const uint32_t r = adj[i];
+    if (i >= n) {
+      if (r) return false;
+      continue;
+    }
+    if ((r & ~live) || ((r >> i) & 1u)) return false;
+    for (uint32_t m = r; m; m &= m - 1u)
+      if (!((adj[lowbit(m)] >> i) & 1u)) return false;
+  }
+  if (pivot >= n || tip >= n || pivot == tip) return false;
+  if (!((fixed >> pivot) & 1u) || ((fixed >> tip) & 1u) || !((adj[pivot] >> tip) & 1u)) return false;
+  return true;
+}
+
+// Finite positions and links longer than 1e-12; scale = longest link; counts the
+// links that are not between two fixed joints.
+__device__ bool geometry_ok(int n, const uint32_t* adj, uint32_t fixed, const double* x0, double* scale,
+                            int* movable_links) {
+  for (int i = 0; i < n; i++)
+    if (!isfinite(x0[2 * i]) || !isfinite(x0[2 * i + 1])) return false;
+  double sc = 0.0;
+  int m = 0;
+  bool ok = true;
+  for (int i = 0; i < n; i++)
+    for (uint32_t r = adj[i] & ~((2u << i) - 1u); r; r &= r - 1u) {
+      const int j = lowbit(r);
+      const double L = sqrt(sqd(x0 + 2 * i, x0 + 2 * j));
+      if (!(L > 1e-12)) ok = false;
+      if (L > sc) sc = L;
+      if (!(((fixed >> i) & 1u) && ((fixed >> j) & 1u))) m++;
+    }
+  *scale = sc;
+  *movable_links = m;
+  return ok;
+}
+
+// Rounds of the graphical solver.  When ord != nullptr the entries are stored as
+// (k | a << 8 | b << 16) in ord[s * stride] and the entry index of joint k in
+// idx[k * stride].  Returns true when every joint is placed.
+__device__ bool solve_rounds(int n, const uint32_t* adj, uint32_t fixed, int tip, uint32_t* ord, uint8_t* idx,
+                             int stride, int* nd_out, int* depth_out) {
+  uint32_t known = fixed | (1u << tip);
+  int nd = 0, depth = 0;
+  for (;;) {
+    uint32_t now = 0u;
+    for (int k = 0; k < n; k++) {
+      if ((known >> k) & 1u) continue;
+      const uint32_t kn = adj[k] & known;
+      if (popc(kn) < 2) continue;
+      if (ord) {
+        const int a = lowbit(kn);
+        const int b = lowbit(kn & (kn - 1u));
+        ord[nd * stride] = (uint32_t)k | ((uint32_t)a << 8) | ((uint32_t)b << 16);
+        idx[k * stride] = (uint8_t)nd;
+      }
+      nd++;
+      now |= 1u << k;
+    }
+    if (!now) break;
+    known |= now;
+    depth++;
+  }
+  *nd_out = nd;
+  *depth_out = depth;
+  return known == live_mask(n);
+}
+
+__global__ void __launch_bounds__(kPrepBlock) solve_order_kernel(PrepArgs A) {
+  __shared__ uint32_t ord_l[kMaxJ * kPrepBlock];
+  __shared__ uint8_t idx_l[kMaxJ * kPrepBlock];
   const int tid = threadIdx.x;
   const int c = blockIdx.x * blockDim.x + tid;
   if (c >= A.B) return;
@@ -38,60 +112,15 @@ __global__ void __launch_bounds__(kPrepBlock) prep_kernel(PrepArgs A) {
   const uint32_t* adj = A.adj + (size_t)c * J;
   const uint32_t fixed = A.fixed[c];
   const int pivot = A.motor[2 * c], tip = A.motor[2 * c + 1];
-
-  // ---- integer structure (same rules as links_solve_order documents)
-  bool ok = n >= 3 && n <= J;
-  const uint32_t live = live_mask(n);
-  if (ok && (fixed & ~live)) ok = false;
-  for (int i = 0; ok && i < J; i++) {
-    uint32_t r = adj[i];
-    if (i >= n) {
-      if (r) ok = false;
-      continue;
-    }
-    if ((r & ~live) || ((r >> i) & 1u)) {
-      ok = false;
-      break;
-    }
-    for (uint32_t m = r; m; m &= m - 1u) {
-      int j = lowbit(m);
-      if (!((adj[j] >> i) & 1u)) ok = false;
-    }
-  }
-  if (ok && (pivot >= n || tip >= n || pivot == tip)) ok = false;
-  if (ok && (!((fixed >> pivot) & 1u) || ((fixed >> tip) & 1u) || !((adj[pivot] >> tip) & 1u))) ok = false;
-
+  const bool ok = structure_ok(J, n, adj, fixed, pivot, tip);
   int nd = 0, depth = 0;
   bool complete = false;
-  if (ok) {
-    // ---- rounds of the graphical solver
-    uint32_t known = fixed | (1u << tip);
-    for (;;) {
-      uint32_t now = 0u;
-      for (int k = 0; k < n; k++) {
-        if ((known >> k) & 1u) continue;
-        uint32_t kn = adj[k] & known;
-        if (popc(kn) < 2) continue;
-        int a = lowbit(kn);
-        int b = lowbit(kn & (kn - 1u));
-        ord_l[nd][tid] = (uint32_t)k | ((uint32_t)a << 8) | ((uint32_t)b << 16);
-        idx_l[k][tid] = (uint8_t)nd;
-        nd++;
-        now |= 1u << k;
-      }
-      if (!now) break;
-      known |= now;
-      depth++;
-    }
-    complete = known == live;
-  }
-
-  // ---- solve-order outputs
+  if (ok) complete = solve_rounds(n, adj, fixed, tip, ord_l + tid, idx_l + tid, kPrepBlock, &nd, &depth);
   if (A.order) {
     int8_t* o = A.order + (size_t)c * J * 3;
     for (int s = 0; s < J; s++) {
-      bool has = ok && s < nd;
-      uint32_t e = has ? ord_l[s][tid] : 0u;
+      const bool has = ok && s < nd;
+      const uint32_t e = has ? ord_l[s * kPrepBlock + tid] : 0u;
       o[3 * s + 0] = has ? (int8_t)(e & 0xFF) : (int8_t)-1;
       o[3 * s + 1] = has ? (int8_t)((e >> 8) & 0xFF) : (int8_t)-1;
       o[3 * s + 2] = has ? (int8_t)((e >> 16) & 0xFF) : (int8_t)-1;
@@ -99,56 +128,134 @@ __global__ void __launch_bounds__(kPrepBlock) prep_kernel(PrepArgs A) {
   }
   if (A.n_dyads) A.n_dyads[c] = ok ? (uint8_t)nd : 0;
   if (A.depth) A.depth[c] = ok ? (uint8_t)depth : 0;
-  if (!A.sim) {
-    A.status[c] = !ok ? 5 : (complete ? 0 : 4);
-    return;
-  }
+  A.status[c] = !ok ? 5 : (complete ? 0 : 4);
+}
 
-  // ---- simulation records
+// ---- simulation set-up, pass 1: status of malformed / unsolvable candidates,
+// solve-order length D of the others and a per-workgroup histogram of D.
+__global__ void __launch_bounds__(kSortBlock) count_kernel(PrepArgs A) {
+  __shared__ int32_t hist[kMaxJ];
+  const int tid = threadIdx.x;
+  if (tid < kMaxJ) hist[tid] = 0;
+  __syncthreads();
+  const int c = blockIdx.x * blockDim.x + tid;
+  if (c < A.B) {
+    const int J = A.J;
+    const int n = A.n[c];
+    const uint32_t* adj = A.adj + (size_t)c * J;
+    const uint32_t fixed = A.fixed[c];
+    const int pivot = A.motor[2 * c], tip = A.motor[2 * c + 1];
+    bool ok = structure_ok(J, n, adj, fixed, pivot, tip);
+    double scale = 0.0;
+    int movable = 0;
+    if (ok) ok = geometry_ok(n, adj, fixed, A.x0 + (size_t)c * J * 2, &scale, &movable);
+    int nd = 0, depth = 0;
+    bool complete = false;
+    if (ok) complete = solve_rounds(n, adj, fixed, tip, nullptr, nullptr, 0, &nd, &depth);
+    uint8_t st = !ok ? 5 : (complete ? kPending : 4);
+    A.status[c] = st;
+    A.dlen[c] = st == kPending ? (uint8_t)nd : (uint8_t)0xFF;
+    if (st != kPending) {
+      A.fail_step[c] = -1;
+      if (A.esc_step) A.esc_step[c] = -1;
+    } else {
+      atomicAdd(&hist[nd], 1);  // LDS: the counts do not depend on the order
+    }
+  }
+  __syncthreads();
+  if (tid < kMaxJ) A.block_hist[(size_t)blockIdx.x * kMaxJ + tid] = hist[tid];
+}
+
+// pass 2: exclusive scan of every bucket's per-workgroup counts (one workgroup per D)
+__global__ void __launch_bounds__(1024) offsets_kernel(int32_t nblocks, const int32_t* block_hist,
+                                                        int32_t* block_off, int32_t* counters) {
+  __shared__ int32_t s[1024];
+  __shared__ int32_t carry;
+  const int d = blockIdx.x;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < nblocks; base += 1024) {
+    const int i = base + threadIdx.x;
+    const int v = i < nblocks ? block_hist[(size_t)i * kMaxJ + d] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 1; w < 1024; w <<= 1) {
+      const int add = threadIdx.x >= w ? s[threadIdx.x - w] : 0;
+      __syncthreads();
+      s[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (i < nblocks) block_off[(size_t)i * kMaxJ + d] = carry + s[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += s[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) counters[kCntHist + d] = carry;
+}
+
+// pass 2b: bucket starts, largest D first, and the work counters
+__global__ void starts_kernel(int32_t* counters) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int32_t off = 0;
+  for (int d = kMaxJ - 1; d >= 0; d--) {
+    counters[kCntOff + d] = off;
+    counters[kCntCur + d] = off;
+    off += counters[kCntHist + d];
+  }
+  counters[kCntItems] = off;
+  counters[kCntNext] = 0;
+}
+
+// pass 3: position of every pending candidate in the sorted work list (largest D
+// first, candidate index within a bucket) and its records at that position.
+__global__ void __launch_bounds__(kSortBlock) fill_kernel(PrepArgs A) {
+  __shared__ uint32_t ord_l[kMaxJ * kSortBlock];
+  __shared__ uint8_t idx_l[kMaxJ * kSortBlock];
+  __shared__ int32_t wave_cnt[kSortBlock / kWave][kMaxJ];
+  const int tid = threadIdx.x;
+  const int w = tid >> 6;
+  const int lane = tid & 63;
+  const int c = blockIdx.x * blockDim.x + tid;
+  const int myd = c < A.B ? A.dlen[c] : 0xFF;
+  // rank among the lanes of this wave with the same D, then among earlier waves
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  int rank = 0;
+  for (int d = 0; d < kMaxJ; d++) {
+    const uint64_t m = __ballot(myd == d);
+    if (myd == d) rank = __popcll(m & below);
+    if (lane == 0) wave_cnt[w][d] = __popcll(m);
+  }
+  __syncthreads();
+  if (myd == 0xFF) return;
+  for (int v = 0; v < w; v++) rank += wave_cnt[v][myd];
+  const int p = A.counters[kCntOff + myd] + A.block_off[(size_t)blockIdx.x * kMaxJ + myd] + rank;
+
+  const int J = A.J;
+  const int Bs = A.Bs;
+  const int n = A.n[c];
+  const uint32_t* adj = A.adj + (size_t)c * J;
+  const uint32_t fixed = A.fixed[c];
+  const int pivot = A.motor[2 * c], tip = A.motor[2 * c + 1];
   const double* x0 = A.x0 + (size_t)c * J * 2;
+  int nd = 0, depth = 0;
+  solve_rounds(n, adj, fixed, tip, ord_l + tid, idx_l + tid, kSortBlock, &nd, &depth);
   double scale = 0.0;
-  if (ok) {
-    for (int i = 0; i < n; i++)
-      if (!isfinite(x0[2 * i]) || !isfinite(x0[2 * i + 1])) ok = false;
-  }
-  int redundant = 0;
-  if (ok) {
-    for (int i = 0; i < n; i++)
-      for (uint32_t m = adj[i] & ~((2u << i) - 1u); m; m &= m - 1u) {
-        int j = lowbit(m);
-        double L = sqrt(sqd(x0 + 2 * i, x0 + 2 * j));
-        if (!(L > 1e-12)) ok = false;
-        if (L > scale) scale = L;
-        if (!(((fixed >> i) & 1u) && ((fixed >> j) & 1u))) redundant++;
-      }
-  }
-  if (!ok) {
-    A.status[c] = 5;
-    A.fail_step[c] = -1;
-    if (A.esc_step) A.esc_step[c] = -1;
-    return;
-  }
-  if (!complete) {
-    A.status[c] = 4;
-    A.fail_step[c] = -1;
-    if (A.esc_step) A.esc_step[c] = -1;
-    return;
-  }
-  // links outside the solve order: all but the actuator arm and 2 per placed joint
-  redundant -= 1 + 2 * nd;
-
+  int movable = 0;
+  geometry_ok(n, adj, fixed, x0, &scale, &movable);
   const int D = nd;
+  // links outside the solve order: all but the actuator arm and two per placed joint
+  const int redundant = movable - 1 - 2 * nd;
   auto slot_of = [&](int j) -> int {
     if (j == tip) return D;
     if ((fixed >> j) & 1u) return D + 1 + popc(fixed & ((1u << j) - 1u));
-    return idx_l[j][tid];
+    return idx_l[j * kSortBlock + tid];
   };
   CandMeta m;
   m.D = (uint8_t)D;
   m.n = (uint8_t)n;
   int out = A.out_joint;
   uint32_t flags = redundant > 0 ? kFlagRedundant : 0u;
-  if (out < 0) out = D > 0 ? (int)(ord_l[D - 1][tid] & 0xFF) : tip;
+  if (out < 0) out = D > 0 ? (int)(ord_l[(D - 1) * kSortBlock + tid] & 0xFF) : tip;
   if (out >= n) {
     flags |= kFlagNoPath;
     m.out_slot = 0;
@@ -156,7 +263,8 @@ __global__ void __launch_bounds__(kPrepBlock) prep_kernel(PrepArgs A) {
     m.out_slot = (uint8_t)slot_of(out);
   }
   m.flags = (uint8_t)flags;
-  A.meta[c] = m;
+  A.meta[p] = m;
+  A.perm[p] = c;
 
   const double px = x0[2 * pivot], py = x0[2 * pivot + 1];
   const double vx = x0[2 * tip] - px, vy = x0[2 * tip + 1] - py;
@@ -170,10 +278,10 @@ __global__ void __launch_bounds__(kPrepBlock) prep_kernel(PrepArgs A) {
   cd.deg_thr = 1e-12 * scale2;
   cd.drift_thr = A.tau_drift * scale;
   cd.pad = 0.0;
-  A.cd[c] = cd;
+  A.cd[p] = cd;
 
-  // FP32 thresholds and error units (a computed position carries at most a few
-  // ulps of its magnitude before amplification)
+  // FP32 thresholds and error units: a computed position carries at most a few
+  // units of FP32 rounding of its magnitude before amplification
   const double u = 4.0 * 5.9604644775390625e-08;
   CandF32 cf;
   cf.px = (float)px;
@@ -184,67 +292,38 @@ __global__ void __launch_bounds__(kPrepBlock) prep_kernel(PrepArgs A) {
   cf.KB = (float)(4.0 * A.eps_disc * scale2 * scale2);
   cf.CD = (float)(A.eps_disc * scale2);
   cf.EB = (float)(A.eps_branch * scale);
-  cf.EP = (float)(A.path_tol * scale);
   cf.U2 = (float)(u * 2.0 * scale);
   cf.TS = (float)(2.0 * scale);
   cf.u = (float)u;
   cf.DG = (float)(1e-12 * scale2);
-  cf.pad[0] = cf.pad[1] = cf.pad[2] = 0.f;
-  A.cf[c] = cf;
+  cf.pad[0] = cf.pad[1] = cf.pad[2] = cf.pad[3] = 0.f;
+  A.cf[p] = cf;
 
-  DyadF32* df = A.df + (size_t)c * J;
-  DyadF64* dd = A.dd + (size_t)c * J;
   for (int s = 0; s < D; s++) {
-    uint32_t e = ord_l[s][tid];
-    int k = e & 0xFF, a = (e >> 8) & 0xFF, b = (e >> 16) & 0xFF;
-    double ra2 = sqd(x0 + 2 * k, x0 + 2 * a);
-    double rb2 = sqd(x0 + 2 * k, x0 + 2 * b);
-    double ra = sqrt(ra2), rb = sqrt(rb2);
-    double sum = ra + rb, dif = ra - rb;
+    const uint32_t e = ord_l[s * kSortBlock + tid];
+    const int k = e & 0xFF, a = (e >> 8) & 0xFF, b = (e >> 16) & 0xFF;
+    const double ra2 = sqd(x0 + 2 * k, x0 + 2 * a);
+    const double rb2 = sqd(x0 + 2 * k, x0 + 2 * b);
+    const double ra = sqrt(ra2), rb = sqrt(rb2);
+    const double sum = ra + rb, dif = ra - rb;
     DyadF64 q;
     q.ra2 = ra2;
     q.rb2 = rb2;
     q.S = sum * sum;
     q.Dm = dif * dif;
-    dd[s] = q;
+    A.dd[(size_t)s * Bs + p] = q;
     DyadF32 f;
     f.S = (float)(sum * sum);
     f.Dm = (float)(dif * dif);
     f.Kc = (float)(0.5 * (ra2 - rb2));
     f.slots = (uint32_t)slot_of(a) | ((uint32_t)slot_of(b) << 8);
-    df[s] = f;
+    A.df[(size_t)s * Bs + p] = f;
   }
-  float2* xs = A.x0s + (size_t)c * J;
-  uint8_t* sj = A.slot_joint + (size_t)c * J;
   for (int j = 0; j < n; j++) {
-    int sl = slot_of(j);
-    xs[sl] = make_float2((float)x0[2 * j], (float)x0[2 * j + 1]);
-    sj[sl] = (uint8_t)j;
+    const int sl = slot_of(j);
+    A.x0s[(size_t)sl * Bs + p] = make_float2((float)x0[2 * j], (float)x0[2 * j + 1]);
+    A.slot_joint[(size_t)sl * Bs + p] = (uint8_t)j;
   }
-  A.status[c] = kPending;
-  atomicAdd(&A.counters[kCntHist + D], 1);
-}
-
-// Exclusive offsets of the D histogram, largest D first (one thread).
-__global__ void bucket_scan_kernel(int32_t* counters, int32_t first_item) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int32_t off = first_item;
-  for (int d = kMaxJ - 1; d >= 0; d--) {
-    int32_t h = counters[kCntHist + d];
-    counters[kCntOff + d] = off;
-    off += h;
-  }
-  counters[kCntItems] = off;
-  counters[kCntNext] = first_item;
-}
-
-__global__ void bucket_scatter_kernel(int32_t B, const uint8_t* status, const CandMeta* meta,
-                                      int32_t* counters, int32_t* perm) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= B || status[c] != kPending) return;
-  int d = meta[c].D;
-  int p = atomicAdd(&counters[kCntOff + d], 1);
-  perm[p] = c;
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v) {
@@ -297,7 +376,7 @@ __global__ void __launch_bounds__(1024) scan_blocks_kernel(int32_t nblocks, int3
 
 __global__ void __launch_bounds__(kScanBlock) write_index_kernel(int32_t B, const uint8_t* status,
                                                                   const int32_t* block_offsets,
-                                                                  int32_t* index, int32_t cap) {
+                                                                  int32_t* index, int32_t cap, int32_t* row_of) {
   __shared__ int32_t s[kScanBlock];
   int c = blockIdx.x * kScanBlock + threadIdx.x;
   int v = (c < B && status[c] == 0) ? 1 : 0;
@@ -311,45 +390,79 @@ __global__ void __launch_bounds__(kScanBlock) write_index_kernel(int32_t B, cons
   }
   int pos = block_offsets[blockIdx.x] + s[threadIdx.x] - v;
   if (v && pos < cap) index[pos] = c;
+  if (v && row_of) row_of[c] = pos < cap ? pos : -1;
 }
 
-// Copies the staged rows of the valid candidates into the compacted output.
-__global__ void gather_rows_kernel(const int32_t* index, const int32_t* total, int32_t cap,
-                                   const uint4* staged, uint4* out, int32_t row_vec4) {
-  int rows = min(*total, cap);
-  for (int r = blockIdx.x; r < rows; r += gridDim.x) {
-    const uint4* src = staged + (size_t)index[r] * row_vec4;
-    uint4* dst = out + (size_t)r * row_vec4;
-    for (int i = threadIdx.x; i < row_vec4; i += blockDim.x) dst[i] = src[i];
-  }
+// selection of the path list over sorted positions p < items
+__device__ inline int path_flag(int p, int items, const int32_t* perm, const uint8_t* status,
+                                const int32_t* row_of, int all_simulated) {
+  if (p >= items) return 0;
+  const int c = perm[p];
+  if (all_simulated) return status[c] <= 3 ? 1 : 0;
+  return (status[c] == 0 && row_of[c] >= 0) ? 1 : 0;
 }
 
-__global__ void gather_rows_f2_kernel(const int32_t* index, const int32_t* total, int32_t cap,
-                                      const float2* staged, float2* out, int32_t row) {
-  int rows = min(*total, cap);
-  for (int r = blockIdx.x; r < rows; r += gridDim.x) {
-    const float2* src = staged + (size_t)index[r] * row;
-    float2* dst = out + (size_t)r * row;
-    for (int i = threadIdx.x; i < row; i += blockDim.x) dst[i] = src[i];
+__global__ void __launch_bounds__(kScanBlock) count_sel_kernel(const int32_t* counters, const int32_t* perm,
+                                                                const uint8_t* status, const int32_t* row_of,
+                                                                int all_simulated, int32_t* block_counts) {
+  __shared__ int32_t s[kScanBlock];
+  const int p = blockIdx.x * kScanBlock + threadIdx.x;
+  s[threadIdx.x] = path_flag(p, counters[kCntItems], perm, status, row_of, all_simulated);
+  __syncthreads();
+  for (int w = kScanBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) block_counts[blockIdx.x] = s[0];
 }
+
+__global__ void __launch_bounds__(kScanBlock) write_sel_kernel(const int32_t* counters, const int32_t* perm,
+                                                                const uint8_t* status, const int32_t* row_of,
+                                                                int all_simulated, const int32_t* block_offsets,
+                                                                int32_t* list) {
+  __shared__ int32_t s[kScanBlock];
+  const int p = blockIdx.x * kScanBlock + threadIdx.x;
+  const int v = path_flag(p, counters[kCntItems], perm, status, row_of, all_simulated);
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 1; w < kScanBlock; w <<= 1) {
+    const int add = threadIdx.x >= w ? s[threadIdx.x - w] : 0;
+    __syncthreads();
+    s[threadIdx.x] += add;
+    __syncthreads();
+  }
+  if (v) list[block_offsets[blockIdx.x] + s[threadIdx.x] - v] = p;
+}
+
 
 }  // namespace
 
-hipError_t launch_prep(const PrepArgs& a, hipStream_t st) {
+hipError_t launch_solve_order(const PrepArgs& a, hipStream_t st) {
   if (a.B <= 0) return hipSuccess;
-  int grid = (a.B + kPrepBlock - 1) / kPrepBlock;
-  hipLaunchKernelGGL(prep_kernel, dim3(grid), dim3(kPrepBlock), 0, st, a);
+  const int grid = (a.B + kPrepBlock - 1) / kPrepBlock;
+  hipLaunchKernelGGL(solve_order_kernel, dim3(grid), dim3(kPrepBlock), 0, st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_bucket_sort(int32_t B, const uint8_t* status, const CandMeta* meta, int32_t* counters,
-                              int32_t* perm, hipStream_t st) {
-  hipLaunchKernelGGL(bucket_scan_kernel, dim3(1), dim3(64), 0, st, counters, 0);
-  if (B > 0) {
-    int grid = (B + 255) / 256;
-    hipLaunchKernelGGL(bucket_scatter_kernel, dim3(grid), dim3(256), 0, st, B, status, meta, counters, perm);
-  }
+int prep_blocks(int32_t B) { return (B + kSortBlock - 1) / kSortBlock; }
+
+hipError_t launch_prep_count(const PrepArgs& a, hipStream_t st) {
+  if (a.B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(count_kernel, dim3(prep_blocks(a.B)), dim3(kSortBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_offsets(const PrepArgs& a, hipStream_t st) {
+  const int nb = prep_blocks(a.B);
+  if (nb > 0) hipLaunchKernelGGL(offsets_kernel, dim3(kMaxJ), dim3(1024), 0, st, nb, a.block_hist, a.block_off,
+                                 a.counters);
+  hipLaunchKernelGGL(starts_kernel, dim3(1), dim3(64), 0, st, a.counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_fill(const PrepArgs& a, hipStream_t st) {
+  if (a.B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3(prep_blocks(a.B)), dim3(kSortBlock), 0, st, a);
   return hipGetLastError();
 }
 
@@ -364,29 +477,29 @@ hipError_t launch_fill_u32(void* p, size_t n_u32, uint32_t v, hipStream_t st) {
 size_t compact_scratch_ints(int32_t B) { return (size_t)((B + kScanBlock - 1) / kScanBlock) + 1; }
 
 hipError_t launch_compact(int32_t B, const uint8_t* status, int32_t* scratch, int32_t* index, int32_t cap,
-                          int32_t* total, hipStream_t st) {
+                          int32_t* total, int32_t* row_of, hipStream_t st) {
   int nb = (B + kScanBlock - 1) / kScanBlock;
   if (nb == 0) {
     return launch_fill_u32(total, 1, 0u, st);
   }
   hipLaunchKernelGGL(count_valid_kernel, dim3(nb), dim3(kScanBlock), 0, st, B, status, scratch);
   hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(1024), 0, st, nb, scratch, total);
-  hipLaunchKernelGGL(write_index_kernel, dim3(nb), dim3(kScanBlock), 0, st, B, status, scratch, index, cap);
+  hipLaunchKernelGGL(write_index_kernel, dim3(nb), dim3(kScanBlock), 0, st, B, status, scratch, index, cap, row_of);
   return hipGetLastError();
 }
 
-hipError_t launch_gather_rows(const int32_t* index, const int32_t* total, int32_t cap, const void* staged,
-                              void* out, size_t row_bytes, hipStream_t st) {
-  if (cap <= 0) return hipSuccess;
-  int grid = cap < 8192 ? cap : 8192;
-  if (row_bytes % 16 == 0) {
-    hipLaunchKernelGGL(gather_rows_kernel, dim3(grid), dim3(128), 0, st, index, total, cap,
-                       (const uint4*)staged, (uint4*)out, (int32_t)(row_bytes / 16));
-  } else {
-    hipLaunchKernelGGL(gather_rows_f2_kernel, dim3(grid), dim3(128), 0, st, index, total, cap,
-                       (const float2*)staged, (float2*)out, (int32_t)(row_bytes / 8));
-  }
+hipError_t launch_select_paths(int32_t B, const int32_t* perm, const uint8_t* status, const int32_t* row_of,
+                               int all_simulated, int32_t* scratch, int32_t* list, int32_t* counters,
+                               hipStream_t st) {
+  const int nb = (B + kScanBlock - 1) / kScanBlock;
+  if (nb == 0) return launch_fill_u32(counters + kCntPath, 1, 0u, st);
+  hipLaunchKernelGGL(count_sel_kernel, dim3(nb), dim3(kScanBlock), 0, st, counters, perm, status, row_of,
+                     all_simulated, scratch);
+  hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(1024), 0, st, nb, scratch, counters + kCntPath);
+  hipLaunchKernelGGL(write_sel_kernel, dim3(nb), dim3(kScanBlock), 0, st, counters, perm, status, row_of,
+                     all_simulated, scratch, list);
   return hipGetLastError();
 }
+
 
 }  // namespace links

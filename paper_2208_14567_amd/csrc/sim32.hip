@@ -31,7 +31,8 @@ __device__ __forceinline__ int mbcnt64(uint64_t m) {
 }
 
 template <int DMAX, int MODE>
-__global__ void __launch_bounds__(256) sim32_kernel(SimArgs A) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DMAX <= 18 ? 3 : 1)))
+sim32_kernel(SimArgs A) {
   extern __shared__ unsigned char smem[];
   const int bd = blockDim.x;
   const int tid = threadIdx.x;
@@ -39,50 +40,145 @@ __global__ void __launch_bounds__(256) sim32_kernel(SimArgs A) {
   float* E = reinterpret_cast<float*>(P + (size_t)A.nslot * bd);
   const int T = A.T;
   const int J = A.J;
-  const bool want_path = A.path != nullptr;
+  // crank table (cos, sin) of every step: in LDS when it fits, so that the step
+  // loop issues no global memory operation
+  constexpr bool tab_lds = (MODE & 2) == 0;
+  float2* tab = reinterpret_cast<float2*>(E + (size_t)A.nslot * bd);
+  if (tab_lds) {
+    for (int i = tid; i < T; i += bd) tab[i] = A.cs32[i];
+    __syncthreads();
+  }
 
-  int cand = -1, t = 0, D = 0, n = 0, out_slot = 0;
-  bool no_path = true;
-  float px = 0.f, py = 0.f, vx = 0.f, vy = 0.f, U = 0.f, KB = 0.f, CD = 0.f, EB = 0.f, EP = 0.f;
+  const int Bs = A.Bs;
+  int cand = -1, item = 0, t = 0, D = 0, n = 0;
+  float px = 0.f, py = 0.f, vx = 0.f, vy = 0.f, U = 0.f, KB = 0.f, CD = 0.f, EB = 0.f;
   float U2 = 0.f, TS = 0.f, uu = 0.f, DG = 0.f;
-  bool force64 = false, path_bad = false;
+  bool force64 = false;
+  int dmax_w = 0;  // largest solve order among the wave's lanes (uniform)
   float cS[DMAX], cDm[DMAX], cKc[DMAX];
-  uint32_t cSl[DMAX];
+  uint32_t cSl[(DMAX + 1) / 2];  // parent slots, two entries per register
 #pragma unroll
   for (int s = 0; s < DMAX; ++s) {
     cS[s] = 0.f;
     cDm[s] = 0.f;
     cKc[s] = 0.f;
-    cSl[s] = 0u;
   }
+#pragma unroll
+  for (int s = 0; s < (DMAX + 1) / 2; ++s) cSl[s] = 0u;
   bool exhausted = false;
+  // Bucket-affine scheduling: the work list is sorted by solve-order length D
+  // (largest first) and split into one bucket per D.  Each wave starts in the
+  // bucket that holds its share of the list and refills only from that bucket, so
+  // the lanes of a wave place the same number of joints per step; an exhausted
+  // bucket sends the wave on to the next smaller bucket that still has work.
+  const int* cnt = A.counters;
+  int bucket = 0;
+  uint32_t done_mask = 0u;  // buckets this wave has seen exhausted (wave-uniform)
+  {
+    const int nw = gridDim.x * (blockDim.x / kWave);
+    const int gw = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    const long long items = cnt[kCntItems];
+    const long long target = (2LL * gw + 1) * items / (2LL * nw);
+    for (int d = kMaxJ - 1; d >= 0; d--) {
+      if (cnt[kCntHist + d] == 0) done_mask |= 1u << d;
+      else if (cnt[kCntOff + d] <= target) bucket = d;
+    }
+  }
+  // Work is claimed one refill ahead: the atomic claim issued at a refill is only
+  // read at the next one, so its latency hides behind the steps in between.
+  int pre_raw = 0;        // the claim's return value (meaningful in lane 0)
+  bool pre_pending = false;
+  int pre_bucket = 0, pre_req = 0;
+  int pre_base = 0, pre_left = 0;  // claimed items not yet handed to lanes
+  const int rm = A.refill_min;
+
+  // next bucket that may still have work: smaller ones first, then larger ones
+  auto pick_bucket = [&]() -> bool {
+    if (!((done_mask >> bucket) & 1u)) return true;
+    for (int d = bucket - 1; d >= 0; --d) {
+      if ((done_mask >> d) & 1u) continue;
+      const int cur = __builtin_amdgcn_readfirstlane(
+          __hip_atomic_load(&A.counters[kCntCur + d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      if (cur < cnt[kCntOff + d] + cnt[kCntHist + d]) {
+        bucket = d;
+        return true;
+      }
+      done_mask |= 1u << d;
+    }
+    for (int d = kMaxJ - 1; d > bucket; --d) {
+      if ((done_mask >> d) & 1u) continue;
+      const int cur = __builtin_amdgcn_readfirstlane(
+          __hip_atomic_load(&A.counters[kCntCur + d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      if (cur < cnt[kCntOff + d] + cnt[kCntHist + d]) {
+        bucket = d;
+        return true;
+      }
+      done_mask |= 1u << d;
+    }
+    return false;
+  };
 
   for (;;) {
     // ---------------- refill idle lanes (wave-uniform control flow)
     uint64_t idle = __ballot(cand < 0);
     int nidle = __popcll(idle);
     if (nidle == kWave && exhausted) break;
-    if (!exhausted && nidle > 0 && (nidle >= A.refill_min || nidle == kWave)) {
-      int leader = __ffsll((unsigned long long)idle) - 1;
-      int base = 0;
-      if (lane_id() == leader) base = atomicAdd(&A.counters[kCntNext], nidle);
-      base = __shfl(base, leader);
-      const int items = A.counters[kCntItems];
-      if (base + nidle >= items) exhausted = true;
-      if (cand < 0) {
-        int p = base + mbcnt64(idle);
-        if (p < items) {
-          int c = A.perm[p];
+    if (!exhausted && nidle > 0 && (nidle >= rm || nidle == kWave)) {
+      int p = -1;
+      // the claim made at the previous refill
+      if (pre_pending) {
+        const int base = __shfl(pre_raw, 0);
+        const int end = cnt[kCntOff + pre_bucket] + cnt[kCntHist + pre_bucket];
+        const int got = min(max(end - base, 0), pre_req);
+        if (got < pre_req) done_mask |= 1u << pre_bucket;
+        pre_base = base;
+        pre_left = got;
+        pre_pending = false;
+      }
+      if (pre_left > 0) {
+        const int m = min(nidle, pre_left);
+        if (cand < 0) {
+          const int r = mbcnt64(idle);
+          if (r < m) p = pre_base + r;
+        }
+        pre_base += m;
+        pre_left -= m;
+        idle = __ballot(cand < 0 && p < 0);
+        nidle = __popcll(idle);
+      }
+      // the rest now; every failed claim marks its bucket done, so this ends
+      // within 33 attempts
+      for (int attempt = 0; attempt <= kMaxJ && nidle > 0; ++attempt) {
+        if (!pick_bucket()) {
+          exhausted = true;
+          break;
+        }
+        const int end = cnt[kCntOff + bucket] + cnt[kCntHist + bucket];
+        const int leader = __ffsll((unsigned long long)idle) - 1;
+        int base = 0;
+        if (lane_id() == leader) base = atomicAdd(&A.counters[kCntCur + bucket], nidle);
+        base = __shfl(base, leader);
+        const int got = min(max(end - base, 0), nidle);
+        if (cand < 0 && p < 0) {
+          const int r = mbcnt64(idle);
+          if (r < got) p = base + r;
+        }
+        if (got == nidle) break;
+        done_mask |= 1u << bucket;  // claimed past its end: exhausted
+        idle = __ballot(cand < 0 && p < 0);
+        nidle = __popcll(idle);
+      }
+      if (cand < 0 && p >= 0) {
+        {
+          const int c = A.perm[p];
           cand = c;
+          item = p;
           t = 0;
-          path_bad = false;
-          CandMeta m = A.meta[c];
+          CandMeta m = A.meta[p];
           D = m.D;
           n = m.n;
-          out_slot = m.out_slot;
-          no_path = (m.flags & kFlagNoPath) != 0;
           force64 = (m.flags & kFlagRedundant) != 0;  // drift checks run in the FP64 pass
-          CandF32 f = A.cf[c];
+          CandF32 f = A.cf[p];
           px = f.px;
           py = f.py;
           vx = f.vx;
@@ -91,39 +187,53 @@ __global__ void __launch_bounds__(256) sim32_kernel(SimArgs A) {
           KB = f.KB;
           CD = f.CD;
           EB = f.EB;
-          EP = f.EP;
           U2 = f.U2;
           TS = f.TS;
           uu = f.u;
           DG = f.DG;
-          const DyadF32* df = A.df + (size_t)c * J;
 #pragma unroll
           for (int s = 0; s < DMAX; ++s) {
             if (s < D) {
-              DyadF32 q = df[s];
+              DyadF32 q = A.df[(size_t)s * Bs + p];
               cS[s] = q.S;
               cDm[s] = q.Dm;
               cKc[s] = q.Kc;
-              cSl[s] = q.slots;
+              if (s & 1)
+                cSl[s >> 1] = (cSl[s >> 1] & 0xFFFFu) | (q.slots << 16);
+              else
+                cSl[s >> 1] = q.slots & 0xFFFFu;
             }
           }
-          const float2* xs = A.x0s + (size_t)c * J;
           for (int sl = 0; sl < n; ++sl) {
-            const float2 q = xs[sl];
+            const float2 q = A.x0s[(size_t)sl * Bs + p];
             P[sl * bd + tid] = q;
             E[sl * bd + tid] = uu * (fabsf(q.x) + fabsf(q.y));  // rounding of x0 to FP32
           }
         }
       }
+      // claim the next refill's work ahead of time, after the record loads so
+      // that nothing waits on it before the next refill
+      if (!exhausted && pre_left == 0 && !((done_mask >> bucket) & 1u)) {
+        pre_req = max(rm, 1);
+        pre_bucket = bucket;
+        if (lane_id() == 0) pre_raw = atomicAdd(&A.counters[kCntCur + bucket], pre_req);
+        pre_pending = true;
+      }
       if (__ballot(cand >= 0) == 0ull) {
         if (exhausted) break;
         continue;
+      }
+      {
+        int dm = cand >= 0 ? D : 0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) dm = max(dm, __shfl_xor(dm, o));
+        dmax_w = __builtin_amdgcn_readfirstlane(dm);
       }
     }
     if (cand < 0) continue;
     {
     // ---------------- one actuator step of this lane's candidate
-    const float2 cs = A.cs32[t];
+    const float2 cs = tab_lds ? tab[t] : A.cs32[t];
     const float tx = fmaf(cs.x, vx, fmaf(-cs.y, vy, px));
     const float ty = fmaf(cs.y, vx, fmaf(cs.x, vy, py));
     P[D * bd + tid] = make_float2(tx, ty);
@@ -131,95 +241,81 @@ __global__ void __launch_bounds__(256) sim32_kernel(SimArgs A) {
 
     bool ev = force64, lock_ev = false;
     int lock_kind = 1;
+    // branch-free placement loop: the trip count is the wave's largest solve order
+    // (uniform); lanes past their own D or past an event keep their old values
 #pragma unroll
     for (int s = 0; s < DMAX; ++s) {
-      if (s < D && !ev) {
-        const uint32_t sl = cSl[s];
-        const int a = sl & 0xFF, b = (sl >> 8) & 0xFF;
-        const float2 pa = P[a * bd + tid];
-        const float2 pb = P[b * bd + tid];
-        const float2 pr = P[s * bd + tid];
+      if (s < dmax_w) {
+      const bool act = s < D && !ev;
+      const uint32_t sl = (s & 1) ? (cSl[s >> 1] >> 16) : cSl[s >> 1];
+      const int a = sl & 0xFF, b = (sl >> 8) & 0xFF;
+      const float2 pa = P[a * bd + tid];
+      const float2 pb = P[b * bd + tid];
+      const float2 pr = P[s * bd + tid];
+      const float dx = pb.x - pa.x, dy = pb.y - pa.y;
+      const float d2 = fmaf(dy, dy, dx * dx);
+      const float S = cS[s], Dm = cDm[s];
+      // discriminant of the circle-circle intersection, 16 area^2 (Heron)
+      const float K = (S - d2) * (d2 - Dm);
+      const float rd = rsq(d2);      // 1/d
+      const float inv = rd * rd;     // 1/d^2
+      const float Kp = fmaxf(K, 1e-30f);
+      const float rK = rsq(Kp);
+      const float sK = Kp * rK;      // sqrt(K)
+      const float be = sK * (0.5f * inv);           // h/d
+      const float al = fmaf(cKc[s], inv, 0.5f);     // foot of the height along a->b
+      const float bx = fmaf(al, dx, pa.x), by = fmaf(al, dy, pa.y);
+      const float ox = -be * dy, oy = be * dx;      // left normal, length h
+      // branch: the intersection nearer the previous position
+      const float sg = fmaf(pr.x - bx, ox, (pr.y - by) * oy);
+      const float sgn = sg >= 0.f ? 1.f : -1.f;
+      const float nx = fmaf(sgn, ox, bx), ny = fmaf(sgn, oy, by);
+      bool write;
+      float Ek = 0.f, Ep = 0.f;
+      if ((MODE & 1) == 0) {
+        // error bound of the parents and of this placement
         const float Ea = E[a * bd + tid];
         const float Eb = E[b * bd + tid];
-        const float Ep = E[s * bd + tid];
-        const float dx = pb.x - pa.x, dy = pb.y - pa.y;
-        const float d2 = fmaf(dy, dy, dx * dx);
-        const float S = cS[s], Dm = cDm[s];
-        // discriminant of the circle-circle intersection, 16 area^2 (Heron)
-        const float K = (S - d2) * (d2 - Dm);
-        const float rd = rsq(d2);      // 1/d
-        const float inv = rd * rd;     // 1/d^2
-        const float Kp = fmaxf(K, 1e-30f);
-        const float rK = rsq(Kp);
-        const float sK = Kp * rK;      // sqrt(K)
-        const float be = sK * (0.5f * inv);           // h/d
-        const float al = fmaf(cKc[s], inv, 0.5f);     // foot of the height along a->b
-        const float bx = fmaf(al, dx, pa.x), by = fmaf(al, dy, pa.y);
-        const float ox = -be * dy, oy = be * dx;      // left normal, length h
-        // branch: the intersection nearer the previous position
-        const float sg = fmaf(pr.x - bx, ox, (pr.y - by) * oy);
-        const float sgn = sg >= 0.f ? 1.f : -1.f;
-        const float nx = fmaf(sgn, ox, bx), ny = fmaf(sgn, oy, by);
-        if (MODE == 0) {
-          // error bound of the parents and of this placement
-          const float Eab = Ea + Eb;
-          const float d = d2 * rd;
-          const float h = 0.5f * sK * rd;
-          const float sensK = 4.f * d * fabsf(fmaf(0.5f, S + Dm, -d2));
-          const float kthr = fmaf(sensK, Eab, KB);
-          const float mthr = fmaf(Eab, fmaf(TS, rd, 1.f), EB + Ep);
-          const bool band = (fabsf(K) < kthr) || (d2 < CD) || (fabsf(sg) < mthr * h);
-          if (band) {
-            ev = true;
-          } else if (K < 0.f) {
-            ev = true;
-            lock_ev = true;
-          } else {
-            const float A2 = 0.5f * (S - Dm) * rK;  // 2 ra rb / sqrt(K)
-            const float Ek = A2 * (Eab + fmaf(uu, fabsf(pa.x) + fabsf(pa.y), U2));
-            P[s * bd + tid] = make_float2(nx, ny);
-            E[s * bd + tid] = Ek;
-          }
-        } else {
-          if (d2 <= DG) {
-            ev = true;
-            lock_ev = true;
-            lock_kind = 2;
-          } else if (K < 0.f) {
-            ev = true;
-            lock_ev = true;
-          } else {
-            P[s * bd + tid] = make_float2(nx, ny);
-          }
-        }
+        Ep = E[s * bd + tid];
+        const float Eab = Ea + Eb;
+        const float d = d2 * rd;
+        const float h = 0.5f * sK * rd;
+        const float sensK = 4.f * d * fabsf(fmaf(0.5f, S + Dm, -d2));
+        const float kthr = fmaf(sensK, Eab, KB);
+        const float mthr = fmaf(Eab, fmaf(TS, rd, 1.f), EB + Ep);
+        const bool band = (int)(fabsf(K) < kthr) | (int)(d2 < CD) | (int)(fabsf(sg) < mthr * h);
+        const bool lock = K < 0.f;
+        lock_ev = lock_ev | (act & !band & lock);
+        ev = ev | (act & (band | lock));
+        write = act & !band & !lock;
+        const float A2 = 0.5f * (S - Dm) * rK;  // 2 ra rb / sqrt(K)
+        Ek = A2 * (Eab + fmaf(uu, fabsf(pa.x) + fabsf(pa.y), U2));
+      } else {
+        const bool deg = d2 <= DG;
+        const bool lock = K < 0.f;
+        lock_kind = (act & deg) ? 2 : lock_kind;
+        lock_ev = lock_ev | (act & (deg | lock));
+        ev = ev | (act & (deg | lock));
+        write = act & !deg & !lock;
+      }
+      P[s * bd + tid] = write ? make_float2(nx, ny) : pr;
+      if ((MODE & 1) == 0) E[s * bd + tid] = write ? Ek : Ep;
       }
     }
 
     bool done = false;
-    if (!ev && want_path && !no_path) {
-      const float2 po = P[out_slot * bd + tid];
-      // the output joint's error bound exceeds the path tolerance: the path of this
-      // candidate will be recomputed in FP64 if it is output
-      if (MODE == 0 && E[out_slot * bd + tid] > EP) path_bad = true;
-      if (A.path_f64) {
-        reinterpret_cast<double2*>(A.path)[(size_t)cand * T + t] = make_double2(po.x, po.y);
-      } else {
-        reinterpret_cast<float2*>(A.path)[(size_t)cand * T + t] = po;
-      }
-    }
     if (ev) {
       if (lock_ev) {
         A.status[cand] = (uint8_t)lock_kind;
         A.fail_step[cand] = (int16_t)t;
         if (A.esc_step) A.esc_step[cand] = -1;
-        if (path_bad && A.write_all) A.refine[atomicAdd(&A.counters[kCntRefine], 1)] = cand;
       } else {
         int i = atomicAdd(&A.counters[kCntEsc], 1);
         EscEntry e;
-        e.cand = cand;
+        e.item = item;
         e.t = (int16_t)t;
         e.from_x0 = force64 ? 1 : 0;
-        e.path_bad = path_bad ? 1 : 0;
+        e.pad = 0;
         A.esc[i] = e;
         float2* dump = A.esc_pos + (size_t)i * J;
         for (int sl = 0; sl < n; ++sl) dump[sl] = P[sl * bd + tid];
@@ -230,7 +326,6 @@ __global__ void __launch_bounds__(256) sim32_kernel(SimArgs A) {
       A.status[cand] = 0;
       A.fail_step[cand] = -1;
       if (A.esc_step) A.esc_step[cand] = -1;
-      if (path_bad) A.refine[atomicAdd(&A.counters[kCntRefine], 1)] = cand;
       done = true;
     }
     if (done) cand = -1;
@@ -241,12 +336,13 @@ __global__ void __launch_bounds__(256) sim32_kernel(SimArgs A) {
 template <int DMAX, int MODE>
 void launch_one(const SimArgs& a, const LaunchCfg& cfg, hipStream_t st) {
   const int bd = cfg.waves * kWave;
-  const size_t lds = (size_t)a.nslot * bd * (sizeof(float2) + sizeof(float));
+  const size_t lds = (size_t)sim32_lds_bytes(a.nslot, cfg.waves, a.T);
   hipLaunchKernelGGL((sim32_kernel<DMAX, MODE>), dim3(cfg.grid), dim3(bd), lds, st, a);
 }
 
 template <int MODE>
 hipError_t dispatch(const SimArgs& a, const LaunchCfg& cfg, hipStream_t st) {
+  if (a.T > kTableLds && (MODE & 2) == 0) return dispatch<MODE | 2>(a, cfg, st);
   switch (sim32_dmax(a.J)) {
     case 5: launch_one<5, MODE>(a, cfg, st); break;
     case 11: launch_one<11, MODE>(a, cfg, st); break;
@@ -275,27 +371,33 @@ int sim32_dmax(int J) {
   return 30;
 }
 
-int sim32_lds_bytes(int nslot, int waves) { return nslot * waves * kWave * (int)(sizeof(float2) + sizeof(float)); }
+int sim32_lds_bytes(int nslot, int waves, int T) {
+  return nslot * waves * kWave * (int)(sizeof(float2) + sizeof(float)) +
+         (T <= kTableLds ? T * (int)sizeof(float2) : 0);
+}
 
 hipError_t launch_sim32(const SimArgs& a, int mode, const LaunchCfg& cfg, hipStream_t st) {
   return mode == 0 ? dispatch<0>(a, cfg, st) : dispatch<1>(a, cfg, st);
 }
 
-int sim32_blocks_per_cu(int J, int mode, int waves, int lds) {
-  int d = sim32_dmax(J);
-  if (mode == 0) {
-    switch (d) {
-      case 5: return occ<5, 0>(waves, lds);
-      case 11: return occ<11, 0>(waves, lds);
-      case 18: return occ<18, 0>(waves, lds);
-      default: return occ<30, 0>(waves, lds);
-    }
-  }
+template <int MODE>
+int occ_d(int d, int waves, int lds) {
   switch (d) {
-    case 5: return occ<5, 1>(waves, lds);
-    case 11: return occ<11, 1>(waves, lds);
-    case 18: return occ<18, 1>(waves, lds);
-    default: return occ<30, 1>(waves, lds);
+    case 5: return occ<5, MODE>(waves, lds);
+    case 11: return occ<11, MODE>(waves, lds);
+    case 18: return occ<18, MODE>(waves, lds);
+    default: return occ<30, MODE>(waves, lds);
+  }
+}
+
+int sim32_blocks_per_cu(int J, int mode, int T, int waves, int lds) {
+  const int d = sim32_dmax(J);
+  const int m = (mode ? 1 : 0) | (T > kTableLds ? 2 : 0);
+  switch (m) {
+    case 0: return occ_d<0>(d, waves, lds);
+    case 1: return occ_d<1>(d, waves, lds);
+    case 2: return occ_d<2>(d, waves, lds);
+    default: return occ_d<3>(d, waves, lds);
   }
 }
 

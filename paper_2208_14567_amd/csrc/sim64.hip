@@ -1,16 +1,25 @@
-// sim64.hip -- FP64 simulation pass.  Runs either every pending candidate from
-// t = 0 (plain FP64 precision) or the candidates the FP32 pass handed over, from
-// the step at which they were handed over.
+// sim64.hip -- FP64 simulation passes.
 //
-// The arithmetic of one step is written as the sequence of correctly rounded
-// double operations below, with no contraction into fused multiply-adds (the
-// library is built with -ffp-contract=off):
+// Work sources:
+//   kFromPerm  every pending candidate from t = 0 (plain FP64 precision);
+//   kFromEsc   the candidates the FP32 pass handed over, from their hand-over step;
+//   kFromPath  the candidates whose coupler path is output, from t = 0, writing
+//              the path rows (the decision is already taken).
+//
+// Two arithmetic variants of one step.  EXACT is the sequence of correctly rounded
+// double operations below, with no fused multiply-adds (the library is built with
+// -ffp-contract=off):
 //   tip   = pivot + (cos t * v_x - sin t * v_y, sin t * v_x + cos t * v_y)
-//   d^2   = dx*dx + dy*dy                           (parents a, b)
+//   d^2   = dx*dx + dy*dy                                         (parents a, b)
 //   K     = (S - d^2)(d^2 - Dm),  S = (ra+rb)^2, Dm = (ra-rb)^2   (16 area^2, Heron)
-//   h     = sqrt(K) / (2 d),  f = (d^2 + ra^2 - rb^2) / (2 d)    (height and its foot)
+//   h     = sqrt(K) / (2 d),  f = (d^2 + ra^2 - rb^2) / (2 d)      (height and its foot)
 //   base  = p_a + (f/d)(dx, dy),  off = (h/d)(-dy, dx)
 //   p     = base + off or base - off, the one nearer the previous position (tie: +)
+// The fast variant evaluates the same intersection with reciprocal square roots
+// refined by two Newton steps and fused multiply-adds (relative error ~1e-15):
+//   1/d = rsq(d^2), alpha = 1/2 + Kc/d^2, beta = sqrt(K)/(2 d^2), Kc = (ra^2-rb^2)/2,
+//   base = p_a + alpha (dx, dy), off = beta (-dy, dx), side by the sign of
+//   (prev - base) . off.
 // A step fails with DEGENERATE when d^2 <= 1e-12 scale^2, LOCKED when K < 0 and
 // DRIFT when a link outside the solve order changes length by more than
 // tau scale (Methodology, "Finding Valid Initial Positions"; the formulas are the
@@ -32,30 +41,40 @@ __device__ inline double sqd2(double ax, double ay, double bx, double by) {
   return dx * dx + dy * dy;
 }
 
-// Length drift of the links outside the solve order (rare: only candidates with
+// 1/sqrt(x) for x > 0: hardware estimate and two Newton steps
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+
+// Length drift of the links outside the solve order (only candidates with
 // redundant links).  Returns true when one of them moved by more than thr.
-__device__ bool drift_check(const SimArgs& A, int cand, int D, int n, const double2* P, int bd, int tid,
+__device__ bool drift_check(const SimArgs& A, int cand, int item, int D, int n, const double2* P, int bd, int tid,
                             double thr) {
   const int J = A.J;
+  const size_t Bs = A.Bs;
   const uint32_t* adj = A.adj + (size_t)cand * J;
-  const uint8_t* sj = A.slot_joint + (size_t)cand * J;
-  const DyadF32* df = A.df + (size_t)cand * J;
+  const uint8_t* sj = A.slot_joint + item;
+  const DyadF32* df = A.df + item;
   const double* x0 = A.x0 + (size_t)cand * J * 2;
   const int pivot = A.motor[2 * cand], tip = A.motor[2 * cand + 1];
   const uint32_t fixed = A.fixed[cand];
   for (int si = 0; si < n; ++si) {
-    const int ji = sj[si];
+    const int ji = sj[si * Bs];
     for (int sk = 0; sk < n; ++sk) {
-      const int jk = sj[sk];
+      const int jk = sj[sk * Bs];
       if (jk <= ji || !((adj[ji] >> jk) & 1u)) continue;
       if ((ji == pivot && jk == tip) || (ji == tip && jk == pivot)) continue;
       bool parent_edge = false;
       if (si < D) {
-        uint32_t q = df[si].slots;
+        const uint32_t q = df[si * Bs].slots;
         parent_edge |= (int)(q & 0xFF) == sk || (int)((q >> 8) & 0xFF) == sk;
       }
       if (sk < D) {
-        uint32_t q = df[sk].slots;
+        const uint32_t q = df[sk * Bs].slots;
         parent_edge |= (int)(q & 0xFF) == si || (int)((q >> 8) & 0xFF) == si;
       }
       if (parent_edge) continue;
@@ -69,7 +88,7 @@ __device__ bool drift_check(const SimArgs& A, int cand, int D, int n, const doub
   return false;
 }
 
-template <int DMAX, int SRC>
+template <int DMAX, int SRC, bool EXACT>
 __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
   extern __shared__ unsigned char smem[];
   const int bd = blockDim.x;
@@ -77,72 +96,106 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
   double2* P = reinterpret_cast<double2*>(smem);  // [nslot][bd]
   const int T = A.T;
   const int J = A.J;
-  const bool want_path = A.path != nullptr;
-  const int cnt_next = SRC == kFromEsc ? kCntEscNext : SRC == kFromRefine ? kCntRefineNext : kCntNext;
-  const int cnt_items = SRC == kFromEsc ? kCntEsc : SRC == kFromRefine ? kCntRefine : kCntItems;
+  const int Bs = A.Bs;
+  const int cnt_next = SRC == kFromEsc ? kCntEscNext : SRC == kFromPath ? kCntPathNext : kCntNext;
+  const int cnt_items = SRC == kFromEsc ? kCntEsc : SRC == kFromPath ? kCntPath : kCntItems;
 
-  int cand = -1, t = 0, D = 0, n = 0, out_slot = 0;
-  bool no_path = true, redundant = false, prefix_bad = false;
+  int cand = -1, item = 0, t = 0, t_end = 0, D = 0, n = 0, out_slot = 0;
+  int64_t row = -1;  // path row (kFromPath)
+  bool redundant = false;
   double px = 0, py = 0, vx = 0, vy = 0, deg_thr = 0, drift_thr = 0;
   bool exhausted = false;
+  // per-entry constants of the lane's candidate, held in registers: S, Dm and
+  // ra^2, rb^2 (EXACT) or Kc = (ra^2 - rb^2)/2 (fast)
+  double cS[DMAX], cDm[DMAX], cA[DMAX], cB[DMAX];
+  uint32_t cSl[DMAX];
+#pragma unroll
+  for (int s = 0; s < DMAX; ++s) {
+    cS[s] = cDm[s] = cA[s] = cB[s] = 0.0;
+    cSl[s] = 0u;
+  }
 
   for (;;) {
-    uint64_t idle = __ballot(cand < 0);
-    int nidle = __popcll(idle);
+    const uint64_t idle = __ballot(cand < 0);
+    const int nidle = __popcll(idle);
     if (nidle == kWave && exhausted) break;
-    if (!exhausted && nidle > 0) {
-      int leader = __ffsll((unsigned long long)idle) - 1;
+    // idle lanes wait until enough of them can be refilled with one claim
+    if (!exhausted && nidle > 0 && (nidle >= A.refill_min || nidle == kWave)) {
+      const int leader = __ffsll((unsigned long long)idle) - 1;
       int base = 0;
       if (__lane_id() == leader) base = atomicAdd(&A.counters[cnt_next], nidle);
       base = __shfl(base, leader);
       const int items = A.counters[cnt_items];
       if (base + nidle >= items) exhausted = true;
       if (cand < 0) {
-        int p = base + mbcnt64(idle);
+        const int p = base + mbcnt64(idle);
         if (p < items) {
-          int c;
+          int it;
           int t0 = 0;
           bool from_x0 = true;
-          prefix_bad = false;
           if (SRC == kFromEsc) {
-            EscEntry e = A.esc[p];
-            c = e.cand;
+            const EscEntry e = A.esc[p];
+            it = e.item;
             t0 = e.t;
             from_x0 = e.from_x0 != 0;
-            prefix_bad = e.path_bad != 0;
-          } else if (SRC == kFromRefine) {
-            c = A.refine[p];
+          } else if (SRC == kFromPath) {
+            it = A.path_list[p];
           } else {
-            c = A.perm[p];
+            it = p;
           }
-          cand = c;
+          const int c = A.perm[it];
+          item = it;
           t = t0;
-          CandMeta m = A.meta[c];
-          D = m.D;
-          n = m.n;
-          out_slot = m.out_slot;
-          no_path = (m.flags & kFlagNoPath) != 0;
-          redundant = (m.flags & kFlagRedundant) != 0;
-          CandF64 f = A.cd[c];
-          px = f.px;
-          py = f.py;
-          vx = f.vx;
-          vy = f.vy;
-          deg_thr = f.deg_thr;
-          drift_thr = f.drift_thr;
-          const uint8_t* sj = A.slot_joint + (size_t)c * J;
-          const double* x0 = A.x0 + (size_t)c * J * 2;
-          const float2* dump = SRC == kFromEsc ? A.esc_pos + (size_t)p * J : nullptr;
-          for (int sl = 0; sl < n; ++sl) {
-            double2 v;
-            if (sl > D || from_x0) {  // fixed joints, or reference positions at t = 0
-              const int j = sj[sl];
-              v = make_double2(x0[2 * j], x0[2 * j + 1]);
-            } else {
-              const float2 q = dump[sl];
-              v = make_double2((double)q.x, (double)q.y);
+          t_end = T;
+          bool take = true;
+          if (SRC == kFromPath) {
+            row = A.write_all ? (int64_t)c : (int64_t)A.path_row[c];
+            const int fs = A.fail_step[c];
+            if (fs >= 0) t_end = fs;  // the path exists up to the failing step
+            take = row >= 0 && t_end > 0;
+          }
+          if (take) {
+            const CandMeta m = A.meta[it];
+            cand = (SRC == kFromPath && (m.flags & kFlagNoPath)) ? -1 : c;
+            D = m.D;
+            n = m.n;
+            out_slot = m.out_slot;
+            redundant = (m.flags & kFlagRedundant) != 0;
+            const CandF64 f = A.cd[it];
+            px = f.px;
+            py = f.py;
+            vx = f.vx;
+            vy = f.vy;
+            deg_thr = f.deg_thr;
+            drift_thr = f.drift_thr;
+#pragma unroll
+            for (int s = 0; s < DMAX; ++s) {
+              if (s < D) {
+                const DyadF64 q = A.dd[(size_t)s * Bs + it];
+                cS[s] = q.S;
+                cDm[s] = q.Dm;
+                if (EXACT) {
+                  cA[s] = q.ra2;
+                  cB[s] = q.rb2;
+                } else {
+                  cA[s] = 0.5 * (q.ra2 - q.rb2);
+                }
+                cSl[s] = A.df[(size_t)s * Bs + it].slots;
+              }
             }
-            P[sl * bd + tid] = v;
+            const double* x0 = A.x0 + (size_t)c * J * 2;
+            const float2* dump = SRC == kFromEsc ? A.esc_pos + (size_t)p * J : nullptr;
+            for (int sl = 0; sl < n; ++sl) {
+              double2 v;
+              if (sl > D || from_x0) {  // fixed joints, or reference positions at t = 0
+                const int j = A.slot_joint[(size_t)sl * Bs + it];
+                v = make_double2(x0[2 * j], x0[2 * j + 1]);
+              } else {
+                const float2 q = dump[sl];
+                v = make_double2((double)q.x, (double)q.y);
+              }
+              P[sl * bd + tid] = v;
+            }
           }
         }
       }
@@ -150,106 +203,130 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
     if (cand >= 0) {
       const double2 cs = A.cs64[t];
       const double ct = cs.x, st = cs.y;
-      P[D * bd + tid] = make_double2(px + (ct * vx - st * vy), py + (st * vx + ct * vy));
-      const DyadF32* df = A.df + (size_t)cand * J;
-      const DyadF64* dd = A.dd + (size_t)cand * J;
+      if (EXACT)
+        P[D * bd + tid] = make_double2(px + (ct * vx - st * vy), py + (st * vx + ct * vy));
+      else
+        P[D * bd + tid] = make_double2(fma(ct, vx, fma(-st, vy, px)), fma(st, vx, fma(ct, vy, py)));
       int fail = 0;
 #pragma unroll
       for (int s = 0; s < DMAX; ++s) {
         if (s < D && fail == 0) {
-          const uint32_t sl = df[s].slots;
-          const DyadF64 q = dd[s];
+          const uint32_t sl = cSl[s];
           const int a = sl & 0xFF, b = (sl >> 8) & 0xFF;
           const double2 pa = P[a * bd + tid];
           const double2 pb = P[b * bd + tid];
+          const double2 pr = P[s * bd + tid];
           const double dx = pb.x - pa.x;
           const double dy = pb.y - pa.y;
-          const double d2 = dx * dx + dy * dy;
-          if (d2 <= deg_thr) {
-            fail = 2;
+          if (EXACT) {
+            const double d2 = dx * dx + dy * dy;
+            if (d2 <= deg_thr) {
+              fail = 2;
+            } else {
+              const double K = (cS[s] - d2) * (d2 - cDm[s]);
+              if (K < 0.0) {
+                fail = 1;
+              } else {
+                const double d = sqrt(d2);
+                const double h = sqrt(K) / (2.0 * d);
+                const double along = (d2 + cA[s] - cB[s]) / (2.0 * d);
+                const double bx = pa.x + (along / d) * dx;
+                const double by = pa.y + (along / d) * dy;
+                const double ox = -(h / d) * dy;
+                const double oy = (h / d) * dx;
+                const double cpx = bx + ox, cpy = by + oy;
+                const double cmx = bx - ox, cmy = by - oy;
+                const double dp2 = (pr.x - cpx) * (pr.x - cpx) + (pr.y - cpy) * (pr.y - cpy);
+                const double dm2 = (pr.x - cmx) * (pr.x - cmx) + (pr.y - cmy) * (pr.y - cmy);
+                P[s * bd + tid] = dp2 <= dm2 ? make_double2(cpx, cpy) : make_double2(cmx, cmy);
+              }
+            }
           } else {
-            const double K = (q.S - d2) * (d2 - q.Dm);
-            if (K < 0.0) {
+            const double d2 = fma(dy, dy, dx * dx);
+            const double K = (cS[s] - d2) * (d2 - cDm[s]);
+            if (d2 <= deg_thr) {
+              fail = 2;
+            } else if (K < 0.0) {
               fail = 1;
             } else {
-              const double d = sqrt(d2);
-              const double h = sqrt(K) / (2.0 * d);
-              const double along = (d2 + q.ra2 - q.rb2) / (2.0 * d);
-              const double bx = pa.x + (along / d) * dx;
-              const double by = pa.y + (along / d) * dy;
-              const double ox = -(h / d) * dy;
-              const double oy = (h / d) * dx;
-              const double cpx = bx + ox, cpy = by + oy;
-              const double cmx = bx - ox, cmy = by - oy;
-              const double2 pr = P[s * bd + tid];
-              const double dp2 = (pr.x - cpx) * (pr.x - cpx) + (pr.y - cpy) * (pr.y - cpy);
-              const double dm2 = (pr.x - cmx) * (pr.x - cmx) + (pr.y - cmy) * (pr.y - cmy);
-              P[s * bd + tid] = dp2 <= dm2 ? make_double2(cpx, cpy) : make_double2(cmx, cmy);
+              const double rd = rsqrt_nr(d2);
+              const double inv = rd * rd;
+              const double Kp = fmax(K, 1e-300);
+              const double sK = Kp * rsqrt_nr(Kp);
+              const double al = fma(cA[s], inv, 0.5);
+              const double be = sK * (0.5 * inv);
+              const double bx = fma(al, dx, pa.x), by = fma(al, dy, pa.y);
+              const double ox = -be * dy, oy = be * dx;
+              const double sg = fma(pr.x - bx, ox, (pr.y - by) * oy);
+              const double sgn = sg >= 0.0 ? 1.0 : -1.0;
+              P[s * bd + tid] = make_double2(fma(sgn, ox, bx), fma(sgn, oy, by));
             }
           }
         }
       }
-      if (fail == 0 && redundant && drift_check(A, cand, D, n, P, bd, tid, drift_thr)) fail = 3;
+      if (fail == 0 && redundant && drift_check(A, cand, item, D, n, P, bd, tid, drift_thr)) fail = 3;
       bool done = false;
-      if (fail != 0) {
+      if (SRC == kFromPath) {
+        double2 po = P[out_slot * bd + tid];
+        if (fail != 0) po = make_double2(__builtin_nan(""), __builtin_nan(""));
+        const int t_stop = fail != 0 ? t_end : t + 1;
+        // a failure here (possible only within rounding of a threshold) leaves the
+        // rest of the row NaN
+        for (int tt = t; tt < t_stop; ++tt) {
+          if (A.path_f64)
+            reinterpret_cast<double2*>(A.path)[row * T + tt] = po;
+          else
+            reinterpret_cast<float2*>(A.path)[row * T + tt] = make_float2((float)po.x, (float)po.y);
+        }
+        if (fail != 0 || ++t >= t_end) done = true;
+      } else if (fail != 0) {
         A.status[cand] = (uint8_t)fail;
         A.fail_step[cand] = (int16_t)t;
-        if (SRC == kFromEsc && prefix_bad && A.write_all)
-          A.refine[atomicAdd(&A.counters[kCntRefine], 1)] = cand;
         done = true;
-      } else {
-        if (want_path && !no_path) {
-          const double2 po = P[out_slot * bd + tid];
-          if (A.path_f64)
-            reinterpret_cast<double2*>(A.path)[(size_t)cand * T + t] = po;
-          else
-            reinterpret_cast<float2*>(A.path)[(size_t)cand * T + t] = make_float2((float)po.x, (float)po.y);
-        }
-        if (++t == T) {
-          A.status[cand] = 0;
-          A.fail_step[cand] = -1;
-          if (SRC == kFromEsc && prefix_bad) A.refine[atomicAdd(&A.counters[kCntRefine], 1)] = cand;
-          done = true;
-        }
+      } else if (++t == T) {
+        A.status[cand] = 0;
+        A.fail_step[cand] = -1;
+        done = true;
       }
       if (done) cand = -1;
     }
   }
 }
 
-template <int DMAX, int SRC>
+template <int DMAX, int SRC, bool EXACT>
 void launch_one(const SimArgs& a, const LaunchCfg& cfg, hipStream_t st) {
   const int bd = cfg.waves * kWave;
   const size_t lds = (size_t)a.nslot * bd * sizeof(double2);
-  hipLaunchKernelGGL((sim64_kernel<DMAX, SRC>), dim3(cfg.grid), dim3(bd), lds, st, a);
+  hipLaunchKernelGGL((sim64_kernel<DMAX, SRC, EXACT>), dim3(cfg.grid), dim3(bd), lds, st, a);
 }
 
-template <int SRC>
+template <int SRC, bool EXACT>
 hipError_t dispatch(const SimArgs& a, const LaunchCfg& cfg, hipStream_t st) {
   switch (sim32_dmax(a.J)) {
-    case 5: launch_one<5, SRC>(a, cfg, st); break;
-    case 11: launch_one<11, SRC>(a, cfg, st); break;
-    case 18: launch_one<18, SRC>(a, cfg, st); break;
-    default: launch_one<30, SRC>(a, cfg, st); break;
+    case 5: launch_one<5, SRC, EXACT>(a, cfg, st); break;
+    case 11: launch_one<11, SRC, EXACT>(a, cfg, st); break;
+    case 18: launch_one<18, SRC, EXACT>(a, cfg, st); break;
+    default: launch_one<30, SRC, EXACT>(a, cfg, st); break;
   }
   return hipGetLastError();
 }
 
-template <int DMAX, int SRC>
+template <int DMAX, int SRC, bool EXACT>
 int occ(int waves, int lds) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sim64_kernel<DMAX, SRC>, waves * kWave, lds) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sim64_kernel<DMAX, SRC, EXACT>, waves * kWave, lds) !=
+      hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
 }
 
-template <int SRC>
+template <int SRC, bool EXACT>
 int occ_for(int J, int waves, int lds) {
   switch (sim32_dmax(J)) {
-    case 5: return occ<5, SRC>(waves, lds);
-    case 11: return occ<11, SRC>(waves, lds);
-    case 18: return occ<18, SRC>(waves, lds);
-    default: return occ<30, SRC>(waves, lds);
+    case 5: return occ<5, SRC, EXACT>(waves, lds);
+    case 11: return occ<11, SRC, EXACT>(waves, lds);
+    case 18: return occ<18, SRC, EXACT>(waves, lds);
+    default: return occ<30, SRC, EXACT>(waves, lds);
   }
 }
 
@@ -257,19 +334,33 @@ int occ_for(int J, int waves, int lds) {
 
 int sim64_lds_bytes(int nslot, int waves) { return nslot * waves * kWave * (int)sizeof(double2); }
 
-hipError_t launch_sim64(const SimArgs& a, int source, const LaunchCfg& cfg, hipStream_t st) {
+hipError_t launch_sim64(const SimArgs& a, int source, bool exact, const LaunchCfg& cfg, hipStream_t st) {
+  if (exact) {
+    switch (source) {
+      case kFromEsc: return dispatch<kFromEsc, true>(a, cfg, st);
+      case kFromPath: return dispatch<kFromPath, true>(a, cfg, st);
+      default: return dispatch<kFromPerm, true>(a, cfg, st);
+    }
+  }
   switch (source) {
-    case kFromEsc: return dispatch<kFromEsc>(a, cfg, st);
-    case kFromRefine: return dispatch<kFromRefine>(a, cfg, st);
-    default: return dispatch<kFromPerm>(a, cfg, st);
+    case kFromEsc: return dispatch<kFromEsc, false>(a, cfg, st);
+    case kFromPath: return dispatch<kFromPath, false>(a, cfg, st);
+    default: return dispatch<kFromPerm, false>(a, cfg, st);
   }
 }
 
-int sim64_blocks_per_cu(int J, int source, int waves, int lds) {
+int sim64_blocks_per_cu(int J, int source, bool exact, int waves, int lds) {
+  if (exact) {
+    switch (source) {
+      case kFromEsc: return occ_for<kFromEsc, true>(J, waves, lds);
+      case kFromPath: return occ_for<kFromPath, true>(J, waves, lds);
+      default: return occ_for<kFromPerm, true>(J, waves, lds);
+    }
+  }
   switch (source) {
-    case kFromEsc: return occ_for<kFromEsc>(J, waves, lds);
-    case kFromRefine: return occ_for<kFromRefine>(J, waves, lds);
-    default: return occ_for<kFromPerm>(J, waves, lds);
+    case kFromEsc: return occ_for<kFromEsc, false>(J, waves, lds);
+    case kFromPath: return occ_for<kFromPath, false>(J, waves, lds);
+    default: return occ_for<kFromPerm, false>(J, waves, lds);
   }
 }
 

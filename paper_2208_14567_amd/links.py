@@ -46,8 +46,8 @@ class SimOut(ctypes.Structure):
 
 EXPORTS = ["links_create", "links_destroy", "links_last_error", "links_version", "links_solve_order",
            "links_sim_opts_default", "links_simulate", "links_normalize_paths", "links_set_tuning",
-           "links_get_tuning", "links_normalize_paths_n", "links_profile", "links_last_timings"]
-TIMING_PASSES = ["prep", "bucket_sort", "fp32_pass", "fp64_pass", "fp64_path_pass", "compaction"]
+           "links_get_tuning", "links_set_option", "links_normalize_paths_n", "links_profile", "links_last_timings"]
+TIMING_PASSES = ["prep_count", "prep_fill", "fp32_pass", "fp64_pass", "compaction", "path_pass"]
 
 _lib = None
 
@@ -81,6 +81,8 @@ def load() -> ctypes.CDLL:
     L.links_set_tuning.restype = ctypes.c_int
     L.links_get_tuning.argtypes = [P] + [ctypes.POINTER(ctypes.c_int)] * 5
     L.links_get_tuning.restype = ctypes.c_int
+    L.links_set_option.argtypes = [P, ctypes.c_char_p, ctypes.c_int]
+    L.links_set_option.restype = ctypes.c_int
     L.links_normalize_paths_n.argtypes = [P, P, P, i32, i32, i32, P, P, P]
     L.links_normalize_paths_n.restype = ctypes.c_int
     L.links_profile.argtypes = [P, ctypes.c_int]
@@ -169,6 +171,9 @@ class Context:
 
     def set_tuning(self, waves32: int, refill_min: int, waves64: int):
         _check(load().links_set_tuning(self._h, waves32, refill_min, waves64), "links_set_tuning")
+
+    def set_option(self, name: str, value: int):
+        _check(load().links_set_option(self._h, name.encode(), int(value)), "links_set_option")
 
     def get_tuning(self) -> dict:
         v = [ctypes.c_int() for _ in range(5)]
