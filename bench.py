@@ -58,6 +58,78 @@ def executed_work(status, fail, esc, nd, T):
     return steps, steps * nd.astype(np.int64)
 
 
+def serve_leg(L, gen, dev, n_req):
+    """Serving loop with requests of 1..200k candidates (log-uniform), n ~ U{4..20}:
+    saturated throughput with every request queued at once, then Poisson arrivals
+    at 0.5 and 0.8 of it."""
+    import torch
+    from paper_2208_14567_amd import serve
+    t0 = time.time()
+    pool_B = 500_000
+    pool = L.to_device(gen.workload("dyad_4_20", pool_B, seed=4), dev)
+    log(f"serving pool of {pool_B} candidates generated in {time.time() - t0:.1f}s")
+    sizes = serve.request_sizes(n_req, seed=4)
+    offs = np.random.default_rng(44).integers(0, pool_B - sizes + 1)
+    total = int(sizes.sum())
+
+    tick_max = 1 << 20
+    reps = -(-tick_max // pool_B)
+    warm = L.DeviceBatch(*[torch.cat([getattr(pool, k)] * reps)[:tick_max] for k in ("n", "adj", "fixed", "motor", "x0")])
+
+    def run(arrivals):
+        srv = serve.Server(capacity=1 << 22, tick_max=tick_max, J=20, T=200)
+        srv.warm(warm)      # workspace and crank tables outside the measurement
+        t = time.perf_counter()
+        reqs = serve.run_stream(srv, pool, sizes, offs, arrivals)
+        torch.cuda.synchronize()
+        span = time.perf_counter() - t
+        st = serve.latency_stats(reqs)
+        st.update({"sims_per_s": total / span, "wall_s": span, "ticks": srv.ticks})
+        return st
+
+    sat = run(np.zeros(n_req))
+    out = {"workload": "requests of 1..200k candidates (log-uniform), n~U{4..20}, T=200, FP32 with FP64 escalation",
+           "requests": n_req, "candidates": total, "saturated": sat}
+    log(f"serving saturated: {sat}")
+    for rho in (0.5, 0.8):
+        rate = rho * sat["sims_per_s"] / sizes.mean()
+        st = run(serve.poisson_arrivals(n_req, rate, seed=4))
+        st["arrival_rate_per_s"] = rate
+        out[f"rho_{rho}"] = st
+        log(f"serving rho={rho}: {st}")
+    return out
+
+
+def end_to_end(L, ctx, host, dev, T):
+    """PCIe-inclusive rate: inputs from pinned host memory, simulation, valid paths
+    and their indices back to pinned host memory (one pass, after warm-up)."""
+    import torch
+    B = host.B
+    pinned = {k: torch.from_numpy(np.ascontiguousarray(v)).pin_memory() for k, v in (
+        ("n", host.n.astype(np.uint8)), ("adj", host.adj.view(np.int32)), ("fixed", host.fixed.view(np.int32)),
+        ("motor", host.motor.astype(np.uint8)), ("x0", host.x0.astype(np.float64)))}
+    dbs = {k: torch.empty(v.shape, dtype=v.dtype, device=dev) for k, v in pinned.items()}
+    db = L.DeviceBatch(dbs["n"], dbs["adj"], dbs["fixed"], dbs["motor"], dbs["x0"])
+    path_h = torch.empty((B, T, 2), dtype=torch.float32).pin_memory()
+    idx_h = torch.empty(B, dtype=torch.int32).pin_memory()
+    res = None
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in pinned:
+            dbs[k].copy_(pinned[k], non_blocking=True)
+        r = ctx.simulate(db, T=T, write=L.WRITE_VALID, cap=B)
+        k = int(r["n_written"].cpu()[0])
+        path_h[:k].copy_(r["path"][:k], non_blocking=True)
+        idx_h[:k].copy_(r["path_index"][:k], non_blocking=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res = {"sims_per_s": B / dt, "ms": dt * 1e3, "valid_paths": k,
+               "h2d_bytes": int(sum(v.numel() * v.element_size() for v in pinned.values())),
+               "d2h_bytes": int(k * T * 8 + k * 4)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +141,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 leg")
     ap.add_argument("--handover", choices=["exact", "fast"], default="exact",
                     help="arithmetic of the FP64 hand-over pass")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the run, copy this many MiB device-to-device (HBM traffic scale for counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
@@ -173,6 +249,12 @@ def main():
                          f"{wall:.2f} s wall ({cpu_model()})"}
         log(f"cpu oracle: {cpu['value']:.0f} sims/s on {threads} threads")
 
+    serving = None
+    if not args.no_serve:
+        serving = serve_leg(L, gen, dev, args.serve_requests)
+
+    e2e = end_to_end(L, ctx, host, dev, T)
+
     res = {
         "metric": METRIC,
         "value": B / sec32,
@@ -194,8 +276,18 @@ def main():
                      "flop_per_dyad_step": FLOP_DYAD_FP32, "dyad_steps": int(dsteps32.sum())},
         "cpu_baseline": cpu,
         "fp64_plain": fp64,
+        "serving": serving,
+        "end_to_end": e2e,
         "stats": stats,
     }
+    if args.copy_probe_mib > 0:
+        nb = args.copy_probe_mib << 20
+        src = torch.empty(nb, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        res["copy_probe_bytes"] = nb
     print(json.dumps(res))
 
 

@@ -201,6 +201,24 @@ int links_normalize_paths(links_ctx* ctx, const float* paths, int32_t P, int32_t
 int links_normalize_paths_n(links_ctx* ctx, const float* paths, const int32_t* count, int32_t cap, int32_t T,
                             int32_t mode, float* out, float* xform, void* stream);
 
+/* Replayable launch sequence.  links_graph_create records the passes of one
+ * links_simulate call with exactly these arguments into a HIP graph (captured on
+ * a private stream; nothing runs yet) and returns it in *graph.  Every replay by
+ * links_graph_launch on `stream` recomputes the outputs from whatever the batch
+ * arrays hold at that time, so a caller may refill the same input buffers and
+ * replay.  The graph keeps the device pointers of batch, out and of the
+ * context's workspace: they must stay valid until links_graph_destroy, and a
+ * links_simulate on the same context that would need a larger workspace fails
+ * with LINKS_ERR_ARG while graphs exist.  Replays of graphs of one context share
+ * its workspace, so they must not overlap in time (same stream, or synchronised).
+ * Profiling events are not recorded in graphs.  Destroy graphs before their
+ * context.  Errors: those of links_simulate, or LINKS_ERR_DEVICE from capture. */
+typedef struct links_graph links_graph;
+int links_graph_create(links_ctx* ctx, const links_batch* batch, const links_sim_opts* opts, links_sim_out* out,
+                       links_graph** graph);
+int links_graph_launch(links_graph* graph, void* stream);
+void links_graph_destroy(links_graph* graph);
+
 /* Kernel timing.  With profiling enabled the next links_simulate records HIP
  * events around each of its passes on the call's stream; links_last_timings
  * synchronises with the last recorded event and writes the elapsed milliseconds

@@ -45,9 +45,7 @@ struct links_ctx {
   int device = 0;
   int num_cu = 0;
   std::map<std::string, Buf> bufs;
-  int table_T = 0;
-  std::vector<double> cs64_host;
-  std::vector<float> cs32_host;
+  std::map<int, bool> tables;  // crank tables uploaded, by T
   // launch parameters (see links_set_tuning)
   int waves32 = 1;
   int refill_min = 48;
@@ -62,6 +60,16 @@ struct links_ctx {
   hipEvent_t ev[LINKS_TIMING_PASSES + 1] = {};
   bool ev_used[LINKS_TIMING_PASSES] = {};
   bool ev_ready = false;
+  // graph capture: passes are enqueued without profiling events, and workspace
+  // held by live graphs is never reallocated
+  bool capturing = false;
+  int graphs = 0;
+};
+
+struct links_graph {
+  links_ctx* ctx = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -69,6 +77,10 @@ namespace {
 int ensure(links_ctx* ctx, const char* name, size_t bytes, void** out) {
   Buf& b = ctx->bufs[name];
   if (b.bytes < bytes) {
+    if (ctx->graphs > 0)
+      return fail(LINKS_ERR_ARG, "workspace %s must grow but %d graph(s) of this context use it; destroy them first",
+                  name, ctx->graphs);
+    if (ctx->capturing) return fail(LINKS_ERR_ARG, "workspace %s would be allocated during capture", name);
     if (b.p) {
       hipError_t e = hipFree(b.p);
       b.p = nullptr;
@@ -110,34 +122,37 @@ int check_batch(const links_batch* b) {
   return LINKS_OK;
 }
 
-// theta_t = 2 pi t / T, counter-clockwise, evaluated in double on the host
+// theta_t = 2 pi t / T, counter-clockwise, evaluated in double on the host; one
+// table per T, so that a recorded graph keeps its own table
 int crank_table(links_ctx* ctx, int T, hipStream_t st, float2** cs32, double2** cs64) {
-  int rc = ensure_t(ctx, "cs64", (size_t)T, cs64);
+  const std::string k64 = "cs64:" + std::to_string(T), k32 = "cs32:" + std::to_string(T);
+  int rc = ensure_t(ctx, k64.c_str(), (size_t)T, cs64);
   if (rc) return rc;
-  rc = ensure_t(ctx, "cs32", (size_t)T, cs32);
+  rc = ensure_t(ctx, k32.c_str(), (size_t)T, cs32);
   if (rc) return rc;
-  if (ctx->table_T != T) {
-    ctx->cs64_host.resize(2 * (size_t)T);
-    ctx->cs32_host.resize(2 * (size_t)T);
+  if (!ctx->tables[T]) {
+    if (ctx->capturing) return fail(LINKS_ERR_ARG, "crank table would be uploaded during capture");
+    std::vector<double> h64(2 * (size_t)T);
+    std::vector<float> h32(2 * (size_t)T);
     for (int t = 0; t < T; t++) {
       double theta = 2.0 * M_PI * (double)t / (double)T;
       double c = cos(theta), s = sin(theta);
-      ctx->cs64_host[2 * t] = c;
-      ctx->cs64_host[2 * t + 1] = s;
-      ctx->cs32_host[2 * t] = (float)c;
-      ctx->cs32_host[2 * t + 1] = (float)s;
+      h64[2 * t] = c;
+      h64[2 * t + 1] = s;
+      h32[2 * t] = (float)c;
+      h32[2 * t + 1] = (float)s;
     }
-    HIP_CHECK(hipMemcpyAsync(*cs64, ctx->cs64_host.data(), sizeof(double) * 2 * T, hipMemcpyHostToDevice, st));
-    HIP_CHECK(hipMemcpyAsync(*cs32, ctx->cs32_host.data(), sizeof(float) * 2 * T, hipMemcpyHostToDevice, st));
+    HIP_CHECK(hipMemcpyAsync(*cs64, h64.data(), sizeof(double) * 2 * T, hipMemcpyHostToDevice, st));
+    HIP_CHECK(hipMemcpyAsync(*cs32, h32.data(), sizeof(float) * 2 * T, hipMemcpyHostToDevice, st));
     HIP_CHECK(hipStreamSynchronize(st));
-    ctx->table_T = T;
+    ctx->tables[T] = true;
   }
   return LINKS_OK;
 }
 
 // records the boundary event before pass i (i == LINKS_TIMING_PASSES: after the last)
 int mark(links_ctx* ctx, int i, hipStream_t st) {
-  if (!ctx->profile) return LINKS_OK;
+  if (!ctx->profile || ctx->capturing) return LINKS_OK;
   if (!ctx->ev[i]) HIP_CHECK(hipEventCreate(&ctx->ev[i]));
   HIP_CHECK(hipEventRecord(ctx->ev[i], st));
   return LINKS_OK;
@@ -270,8 +285,15 @@ int links_solve_order(links_ctx* ctx, const links_batch* batch, int8_t* order, u
   return LINKS_OK;
 }
 
-int links_simulate(links_ctx* ctx, const links_batch* batch, const links_sim_opts* opts, links_sim_out* out,
-                   void* stream) {
+}  // extern "C"
+
+namespace {
+
+enum Phase { kPrepare = 0, kRun = 1 };
+
+// kPrepare: argument checks, workspace and crank table only; kRun: the whole call
+int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts* opts, links_sim_out* out,
+                  void* stream, int phase) {
   if (!ctx) return fail(LINKS_ERR_ARG, "ctx is NULL");
   int rc = check_batch(batch);
   if (rc) return rc;
@@ -334,6 +356,7 @@ int links_simulate(links_ctx* ctx, const links_batch* batch, const links_sim_opt
   float2* cs32;
   double2* cs64;
   if ((rc = crank_table(ctx, T, st, &cs32, &cs64))) return rc;
+  if (phase == kPrepare) return LINKS_OK;
 
   const size_t elt = opts->path_dtype == LINKS_F64 ? sizeof(double2) : sizeof(float2);
   if (opts->write == LINKS_WRITE_ALL)
@@ -470,8 +493,82 @@ int links_simulate(links_ctx* ctx, const links_batch* batch, const links_sim_opt
     ctx->ev_used[5] = true;
   }
   if ((rc = mark(ctx, 6, st))) return rc;
-  ctx->ev_ready = ctx->profile;
+  ctx->ev_ready = ctx->profile && !ctx->capturing;
   return LINKS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int links_simulate(links_ctx* ctx, const links_batch* batch, const links_sim_opts* opts, links_sim_out* out,
+                   void* stream) {
+  return simulate_impl(ctx, batch, opts, out, stream, kRun);
+}
+
+int links_graph_create(links_ctx* ctx, const links_batch* batch, const links_sim_opts* opts, links_sim_out* out,
+                       links_graph** graph) {
+  if (!graph) return fail(LINKS_ERR_ARG, "graph is NULL");
+  *graph = nullptr;
+  if (!ctx) return fail(LINKS_ERR_ARG, "ctx is NULL");
+  if (ctx->capturing) return fail(LINKS_ERR_ARG, "context is already capturing");
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  hipStream_t st = nullptr;
+  HIP_CHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  // workspace and crank table first, outside the capture
+  rc = simulate_impl(ctx, batch, opts, out, st, kPrepare);
+  if (rc == LINKS_OK) {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) rc = fail(LINKS_ERR_DEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
+  }
+  hipGraph_t g = nullptr;
+  if (rc == LINKS_OK) {
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+      rc = fail(LINKS_ERR_DEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    } else {
+      ctx->capturing = true;
+      rc = simulate_impl(ctx, batch, opts, out, st, kRun);
+      ctx->capturing = false;
+      e = hipStreamEndCapture(st, &g);
+      if (rc == LINKS_OK && e != hipSuccess) rc = fail(LINKS_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    }
+  }
+  hipGraphExec_t x = nullptr;
+  if (rc == LINKS_OK) {
+    hipError_t e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) rc = fail(LINKS_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  (void)hipStreamDestroy(st);
+  if (rc != LINKS_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  links_graph* out_g = new links_graph();
+  out_g->ctx = ctx;
+  out_g->graph = g;
+  out_g->exec = x;
+  ctx->graphs++;
+  *graph = out_g;
+  return LINKS_OK;
+}
+
+int links_graph_launch(links_graph* graph, void* stream) {
+  if (!graph || !graph->exec) return fail(LINKS_ERR_ARG, "graph is NULL");
+  int rc = set_device(graph->ctx);
+  if (rc) return rc;
+  HIP_CHECK(hipGraphLaunch(graph->exec, (hipStream_t)stream));
+  return LINKS_OK;
+}
+
+void links_graph_destroy(links_graph* graph) {
+  if (!graph) return;
+  (void)hipSetDevice(graph->ctx->device);
+  if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+  if (graph->graph) (void)hipGraphDestroy(graph->graph);
+  graph->ctx->graphs--;
+  delete graph;
 }
 
 int links_profile(links_ctx* ctx, int enable) {

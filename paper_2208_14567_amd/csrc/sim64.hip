@@ -282,10 +282,12 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
       } else if (fail != 0) {
         A.status[cand] = (uint8_t)fail;
         A.fail_step[cand] = (int16_t)t;
+        if (SRC == kFromPerm && A.esc_step) A.esc_step[cand] = -1;  // FP64 throughout: never handed over
         done = true;
       } else if (++t == T) {
         A.status[cand] = 0;
         A.fail_step[cand] = -1;
+        if (SRC == kFromPerm && A.esc_step) A.esc_step[cand] = -1;
         done = true;
       }
       if (done) cand = -1;

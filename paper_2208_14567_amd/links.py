@@ -46,7 +46,8 @@ class SimOut(ctypes.Structure):
 
 EXPORTS = ["links_create", "links_destroy", "links_last_error", "links_version", "links_solve_order",
            "links_sim_opts_default", "links_simulate", "links_normalize_paths", "links_set_tuning",
-           "links_get_tuning", "links_set_option", "links_normalize_paths_n", "links_profile", "links_last_timings"]
+           "links_get_tuning", "links_set_option", "links_normalize_paths_n", "links_profile", "links_last_timings",
+           "links_graph_create", "links_graph_launch", "links_graph_destroy"]
 TIMING_PASSES = ["prep_count", "prep_fill", "fp32_pass", "fp64_pass", "compaction", "path_pass"]
 
 _lib = None
@@ -89,6 +90,13 @@ def load() -> ctypes.CDLL:
     L.links_profile.restype = ctypes.c_int
     L.links_last_timings.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
     L.links_last_timings.restype = ctypes.c_int
+    L.links_graph_create.argtypes = [P, ctypes.POINTER(Batch), ctypes.POINTER(SimOpts), ctypes.POINTER(SimOut),
+                                     ctypes.POINTER(P)]
+    L.links_graph_create.restype = ctypes.c_int
+    L.links_graph_launch.argtypes = [P, P]
+    L.links_graph_launch.restype = ctypes.c_int
+    L.links_graph_destroy.argtypes = [P]
+    L.links_graph_destroy.restype = None
     _lib = L
     return L
 
@@ -205,11 +213,8 @@ class Context:
         return order, nd, dp, st
 
     # ------------------------------------------------------------------ simulation
-    def simulate(self, b: DeviceBatch, T: int = 200, precision: int = FP32_RECHECK, write: int = WRITE_NONE,
-                 out_joint: int = -1, path_dtype: int = F32, cap: Optional[int] = None, eps_disc: float = 1e-6,
-                 eps_branch: float = 1e-5, tau_drift: float = 1e-4, out: Optional[dict] = None, stream=None):
-        """Returns a dict of device tensors: status, fail_step, esc_step and, by write
-        mode, path ([B,T,2] or [cap,T,2]), path_index and n_written."""
+    def _sim_args(self, b: DeviceBatch, T, precision, write, out_joint, path_dtype, cap, eps_disc, eps_branch,
+                  tau_drift, out):
         dev = b.n.device
         B = b.B
         o = out or {}
@@ -228,16 +233,37 @@ class Context:
             nw = o.get("n_written") if o.get("n_written") is not None else torch.empty(1, dtype=torch.int32, device=dev)
         opts = SimOpts(T, precision, eps_disc, eps_branch, tau_drift, out_joint, write, path_dtype)
         so = SimOut(_ptr(status), _ptr(fail), _ptr(esc), _ptr(path), _ptr(idx), _ptr(nw), cap_v)
-        cb = b.cstruct()
-        _check(load().links_simulate(self._h, ctypes.byref(cb), ctypes.byref(opts), ctypes.byref(so), _stream(stream)),
-               "links_simulate")
         res = {"status": status, "fail_step": fail, "esc_step": esc}
         if path is not None:
             res["path"] = path
         if idx is not None:
             res["path_index"] = idx
             res["n_written"] = nw
+        return b.cstruct(), opts, so, res
+
+    def simulate(self, b: DeviceBatch, T: int = 200, precision: int = FP32_RECHECK, write: int = WRITE_NONE,
+                 out_joint: int = -1, path_dtype: int = F32, cap: Optional[int] = None, eps_disc: float = 1e-6,
+                 eps_branch: float = 1e-5, tau_drift: float = 1e-4, out: Optional[dict] = None, stream=None):
+        """Returns a dict of device tensors: status, fail_step, esc_step and, by write
+        mode, path ([B,T,2] or [cap,T,2]), path_index and n_written."""
+        cb, opts, so, res = self._sim_args(b, T, precision, write, out_joint, path_dtype, cap, eps_disc, eps_branch,
+                                           tau_drift, out)
+        _check(load().links_simulate(self._h, ctypes.byref(cb), ctypes.byref(opts), ctypes.byref(so), _stream(stream)),
+               "links_simulate")
         return res
+
+    def graph(self, b: DeviceBatch, T: int = 200, precision: int = FP32_RECHECK, write: int = WRITE_NONE,
+              out_joint: int = -1, path_dtype: int = F32, cap: Optional[int] = None, eps_disc: float = 1e-6,
+              eps_branch: float = 1e-5, tau_drift: float = 1e-4, out: Optional[dict] = None) -> "Graph":
+        """Records the launch sequence of ``simulate`` with these arguments into a HIP
+        graph; ``Graph.launch`` replays it on the current stream.  The returned
+        graph holds the batch and output tensors (``Graph.out``)."""
+        cb, opts, so, res = self._sim_args(b, T, precision, write, out_joint, path_dtype, cap, eps_disc, eps_branch,
+                                           tau_drift, out)
+        g = P()
+        _check(load().links_graph_create(self._h, ctypes.byref(cb), ctypes.byref(opts), ctypes.byref(so),
+                                         ctypes.byref(g)), "links_graph_create")
+        return Graph(g, self, b, res)
 
     # ------------------------------------------------------------------ normalisation
     def normalize_paths(self, paths: torch.Tensor, mode: int = NORM_PCA, out: Optional[torch.Tensor] = None,
@@ -260,3 +286,28 @@ class Context:
         _check(load().links_normalize_paths_n(self._h, _ptr(paths), _ptr(count), cap, T, mode, _ptr(out), _ptr(xform),
                                               _stream(stream)), "links_normalize_paths_n")
         return out, xform
+
+
+class Graph:
+    """A recorded links_simulate launch sequence (see links_graph_create)."""
+
+    def __init__(self, handle, ctx: "Context", batch: DeviceBatch, out: dict):
+        self._h = handle
+        self._ctx = ctx      # the context outlives the graph
+        self.batch = batch   # inputs and outputs stay alive with the graph
+        self.out = out
+
+    def launch(self, stream=None):
+        _check(load().links_graph_launch(self._h, _stream(stream)), "links_graph_launch")
+        return self.out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().links_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

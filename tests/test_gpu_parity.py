@@ -109,6 +109,7 @@ def test_fp64_bit_exact(ctx, L, name, B, seed):
     ref = oracle.simulate(b, T=200, path=True, nthreads=NTH)
     assert np.array_equal(r["status"], ref["status"])
     assert np.array_equal(r["fail_step"], ref["fail_step"])
+    assert np.all(r["esc_step"] == -1)          # FP64 throughout: nothing handed over
     same = (r["path"] == ref["path"]) | (np.isnan(r["path"]) & np.isnan(ref["path"]))
     assert same.all(), f"{(~same.all(axis=(1, 2))).sum()} paths differ in some bit"
 
