@@ -32,8 +32,37 @@ METRIC = "mechanism sims/sec (200 steps) FP32+recheck vs FP64 plain; p99 request
 FLOP_DYAD_FP32 = 40   # one placement: d^2, discriminant, 1/d, sqrt K, foot, normal, branch, lock/band tests
 FLOP_TIP = 8          # crank rotation of the tip per step
 FLOP_DYAD_FP64 = 42   # the FP64 step formula (two sqrt, four divisions, both branch distances)
-FP32_PEAK = 157.3e12
+FP32_PEAK = 157.3e12            # published FP32 vector peak (packed FMA)
+FP32_PEAK_NONPACKED = 78.6e12   # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA), packed FP32 disabled in the build
 FP64_PEAK = 78.6e12
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sim32_kernel_dyad_6_20_1M_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2208_14567_amd", "csrc", f) for f in ("sim32.hip", "common.h", "kernels.h")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile():
+    """HBM bytes per launch of the FP32 pass from the committed counter summary,
+    or None when the summary is missing or the kernel sources changed since."""
+    try:
+        lines = open(TRAFFIC_PROFILE).read().splitlines()
+    except OSError:
+        return None
+    vals = {}
+    for line in lines:
+        if line.startswith("traffic_bytes_per_launch:") or line.startswith("source_hash:"):
+            k, v = line.split(":", 1)
+            vals[k] = v.strip()
+    if vals.get("source_hash") != kernel_source_hash() or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def log(*a):
@@ -58,7 +87,7 @@ def executed_work(status, fail, esc, nd, T):
     return steps, steps * nd.astype(np.int64)
 
 
-def serve_leg(L, gen, dev, n_req):
+def serve_leg(L, gen, dev, n_req, cfg=None):
     """Serving loop with requests of 1..200k candidates (log-uniform), n ~ U{4..20}:
     saturated throughput with every request queued at once, then Poisson arrivals
     at 0.5 and 0.8 of it."""
@@ -78,6 +107,10 @@ def serve_leg(L, gen, dev, n_req):
 
     def run(arrivals):
         srv = serve.Server(capacity=1 << 22, tick_max=tick_max, J=20, T=200)
+        if cfg:
+            from paper_2208_14567_amd import tune
+            for lane in srv.lanes:
+                tune.apply(lane.ctx, cfg)
         srv.warm(warm)      # workspace and crank tables outside the measurement
         t = time.perf_counter()
         reqs = serve.run_stream(srv, pool, sizes, offs, arrivals)
@@ -139,9 +172,10 @@ def main():
     ap.add_argument("--T", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 leg")
-    ap.add_argument("--handover", choices=["exact", "fast"], default="exact",
+    ap.add_argument("--handover", choices=["exact", "fast"], default="fast",
                     help="arithmetic of the FP64 hand-over pass")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
+    ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch parameters")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device (HBM traffic scale for counters)")
@@ -161,6 +195,12 @@ def main():
     db = L.to_device(host, dev)
     ctx = L.Context(0)
     ctx.set_option("exact_handover", 1 if args.handover == "exact" else 0)
+    from paper_2208_14567_amd import tune
+    tuned = None
+    if not args.no_tune:
+        t0 = time.time()
+        tuned = tune.autotune(ctx, db, T=T, precision=L.FP32_RECHECK, use_cache=False)
+        log(f"autotune: {tuned['config']} ({tuned['ms']:.3f} ms, {tuned['measurements']} runs, {time.time() - t0:.1f}s)")
     out = {"status": torch.empty(B, dtype=torch.uint8, device=dev),
            "fail_step": torch.empty(B, dtype=torch.int16, device=dev),
            "esc_step": torch.empty(B, dtype=torch.int16, device=dev),
@@ -170,30 +210,30 @@ def main():
     norm_out = torch.empty((B, T, 2), dtype=torch.float32, device=dev)
     norm_xf = torch.empty((B, 5), dtype=torch.float32, device=dev)
 
-    def step(precision):
-        ctx.simulate(db, T=T, precision=precision, write=L.WRITE_VALID, cap=B, out=out)
-        ctx.normalize_paths_n(out["path"], out["n_written"], L.NORM_PCA, out=norm_out, xform=norm_xf)
+    def step(c, precision):
+        c.simulate(db, T=T, precision=precision, write=L.WRITE_VALID, cap=B, out=out)
+        c.normalize_paths_n(out["path"], out["n_written"], L.NORM_PCA, out=norm_out, xform=norm_xf)
 
-    def run(precision, label):
+    def run(c, precision, label):
         for _ in range(args.warmup):
-            step(precision)
+            step(c, precision)
         torch.cuda.synchronize()
-        ctx.profile(True)
+        c.profile(True)
         passes = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            step(precision)
-            passes.append(ctx.last_timings())
+            step(c, precision)
+            passes.append(c.last_timings())
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        ctx.profile(False)
+        c.profile(False)
         mean = {k: float(np.mean([p[k] for p in passes])) for k in passes[0]}
         log(f"{label}: {dt / args.steps * 1e3:.3f} ms/step, passes (ms): " +
             ", ".join(f"{k} {v:.3f}" for k, v in mean.items()))
         return dt / args.steps, mean
 
-    sec32, pass32 = run(L.FP32_RECHECK, "fp32+fp64-escalation")
+    sec32, pass32 = run(ctx, L.FP32_RECHECK, "fp32+fp64-escalation")
     st = out["status"].cpu().numpy()
     fs = out["fail_step"].cpu().numpy()
     es = out["esc_step"].cpu().numpy()
@@ -218,13 +258,20 @@ def main():
 
     fp64 = None
     if not args.no_fp64:
-        sec64, pass64 = run(L.FP64, "fp64 plain")
+        ctx64 = L.Context(0)
+        tuned64 = None
+        if not args.no_tune:
+            tuned64 = tune.autotune(ctx64, db, T=T, precision=L.FP64, use_cache=False,
+                                    space={"chunk": tune.SPACE["chunk"], "refill64": [1, 8, 32]})
+            log(f"autotune fp64: {tuned64['config']} ({tuned64['ms']:.3f} ms)")
+        sec64, pass64 = run(ctx64, L.FP64, "fp64 plain")
         st64 = out["status"].cpu().numpy()
         fs64 = out["fail_step"].cpu().numpy()
         d64 = np.where(st64 == 0, T, np.where(fs64 >= 0, fs64, 0)).astype(np.int64)
         flop64 = float((d64 * nd).sum()) * FLOP_DYAD_FP64 + float(d64.sum()) * FLOP_TIP
         fp64 = {"value": B / sec64, "ms_per_step": sec64 * 1e3, "speedup_fp32_recheck_over_fp64": sec64 / sec32,
-                "fp64_pass_ms": pass64["fp64_pass"],
+                "fp64_pass_ms": pass64["fp64_pass"], "passes_ms": pass64,
+                "tuning": tuned64["config"] if tuned64 else None,
                 "roofline": {"bound": "alu", "achieved": flop64 / (pass64["fp64_pass"] * 1e-3) / 1e12,
                              "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
                              "frac": flop64 / (pass64["fp64_pass"] * 1e-3) / FP64_PEAK},
@@ -248,10 +295,16 @@ def main():
                "sample": f"first {sub.B} candidates of the same batch, FP64, {threads} host threads, "
                          f"{wall:.2f} s wall ({cpu_model()})"}
         log(f"cpu oracle: {cpu['value']:.0f} sims/s on {threads} threads")
+        one = host.slice(0, min(B, 40_000))
+        t0 = time.perf_counter()
+        oracle.simulate(one, T=T, nthreads=1)
+        w1 = time.perf_counter() - t0
+        cpu["one_core"] = {"value": one.B / w1, "sample": f"first {one.B} candidates, 1 thread, {w1:.2f} s"}
+        log(f"cpu oracle, one core: {one.B / w1:.0f} sims/s")
 
     serving = None
     if not args.no_serve:
-        serving = serve_leg(L, gen, dev, args.serve_requests)
+        serving = serve_leg(L, gen, dev, args.serve_requests, tuned["config"] if tuned else None)
 
     e2e = end_to_end(L, ctx, host, dev, T)
 
@@ -270,10 +323,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": "dyad_6_20: 1M dyad-built 1-DOF candidates, n~U{6..20}, x0~U[0,1)^2, T=200; "
                                "FP32 with FP64 escalation; valid coupler paths compacted and PCA-normalised",
-                   "candidates": B, "T": T, "seed": 2},
+                   "candidates": B, "T": T, "seed": 2,
+                   "tuning": tuned["config"] if tuned else None},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK, "traffic": None, "kernel": "sim32_kernel (FP32 pass)",
-                     "flop_per_dyad_step": FLOP_DYAD_FP32, "dyad_steps": int(dsteps32.sum())},
+                     "frac": achieved / FP32_PEAK, "traffic": traffic_from_profile(),
+                     "kernel": "sim32_kernel (FP32 pass)", "kernel_ms": t32 * 1e3,
+                     "peak_nonpacked": FP32_PEAK_NONPACKED / 1e12, "frac_nonpacked": achieved / FP32_PEAK_NONPACKED,
+                     "flop_per_dyad_step": FLOP_DYAD_FP32, "flop_per_step": FLOP_TIP,
+                     "dyad_steps": int(dsteps32.sum()), "candidate_steps": int(steps32.sum())},
         "cpu_baseline": cpu,
         "fp64_plain": fp64,
         "serving": serving,

@@ -174,12 +174,20 @@ int links_simulate(links_ctx* ctx, const links_batch* batch, const links_sim_opt
 int links_set_tuning(links_ctx* ctx, int waves32, int refill_min, int waves64);
 /* Named integer options (LINKS_ERR_ARG for an unknown name or value):
  *   "waves32", "refill_min", "waves64"  as in links_set_tuning;
+ *   "chunk"           list items a wave claims with one atomic operation and
+ *                     then hands to its lanes as they free up (1..4096, default 128);
+ *   "spread"          1 (default): waves of the FP32 pass start spread over the
+ *                     solve-order buckets in proportion to their sizes; 0: all
+ *                     start in the largest bucket and move down together;
  *   "refill64"        idle lanes a wave of the FP64 passes waits for before it
  *                     fetches new candidates (1..64, default 32);
- *   "exact_handover"  1 (default): the FP64 hand-over pass evaluates the correctly
- *                     rounded sequence of the FP64 precision; 0: reciprocal square
- *                     roots refined by Newton steps (relative error ~1e-15). */
+ *   "exact_handover"  0 (default): the FP64 hand-over pass uses reciprocal square
+ *                     roots refined by Newton steps (relative error ~1e-15); 1: the
+ *                     correctly rounded sequence of the FP64 precision (the
+ *                     operations of an IEEE double evaluation, as in LINKS_FP64). */
 int links_set_option(links_ctx* ctx, const char* name, int value);
+/* Current value of a named option in *value (LINKS_ERR_ARG for an unknown name). */
+int links_get_option(links_ctx* ctx, const char* name, int* value);
 
 /* Current launch parameters and the persistent grid sizes of the last call (any
  * pointer may be NULL). */

@@ -51,7 +51,9 @@ struct links_ctx {
   int refill_min = 48;
   int waves64 = 1;
   int refill64 = 32;           // refill threshold of the FP64 passes
-  bool exact_handover = true;  // FP64 hand-over pass with the correctly rounded sequence
+  int spread = 1;              // FP32 waves start spread over the solve-order buckets
+  int chunk = 128;             // list items a wave claims per atomic
+  bool exact_handover = false;  // FP64 hand-over pass with the correctly rounded sequence (else rsq + Newton)
   std::map<std::string, int> occ_cache;
   // last call's statistics
   int last_grid32 = 0, last_grid64 = 0;
@@ -235,6 +237,16 @@ int links_set_option(links_ctx* ctx, const char* name, int value) {
   if (k == "waves32") return links_set_tuning(ctx, value, ctx->refill_min, ctx->waves64);
   if (k == "refill_min") return links_set_tuning(ctx, ctx->waves32, value, ctx->waves64);
   if (k == "waves64") return links_set_tuning(ctx, ctx->waves32, ctx->refill_min, value);
+  if (k == "chunk") {
+    if (value < 1 || value > 4096) return fail(LINKS_ERR_ARG, "chunk must be in 1..4096");
+    ctx->chunk = value;
+    return LINKS_OK;
+  }
+  if (k == "spread") {
+    if (value != 0 && value != 1) return fail(LINKS_ERR_ARG, "spread must be 0 or 1");
+    ctx->spread = value;
+    return LINKS_OK;
+  }
   if (k == "refill64") {
     if (value < 1 || value > 64) return fail(LINKS_ERR_ARG, "refill64 must be in 1..64");
     ctx->refill64 = value;
@@ -246,6 +258,20 @@ int links_set_option(links_ctx* ctx, const char* name, int value) {
     return LINKS_OK;
   }
   return fail(LINKS_ERR_ARG, "unknown option '%s'", name);
+}
+
+int links_get_option(links_ctx* ctx, const char* name, int* value) {
+  if (!ctx || !name || !value) return fail(LINKS_ERR_ARG, "NULL argument");
+  const std::string k(name);
+  if (k == "waves32") *value = ctx->waves32;
+  else if (k == "refill_min") *value = ctx->refill_min;
+  else if (k == "waves64") *value = ctx->waves64;
+  else if (k == "refill64") *value = ctx->refill64;
+  else if (k == "chunk") *value = ctx->chunk;
+  else if (k == "spread") *value = ctx->spread;
+  else if (k == "exact_handover") *value = ctx->exact_handover ? 1 : 0;
+  else return fail(LINKS_ERR_ARG, "unknown option '%s'", name);
+  return LINKS_OK;
 }
 
 int links_get_tuning(links_ctx* ctx, int* waves32, int* refill_min, int* waves64, int* grid32, int* grid64) {
@@ -441,6 +467,8 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   sa.path_f64 = opts->path_dtype == LINKS_F64;
   sa.nslot = J;
   sa.refill_min = ctx->refill_min;
+  sa.spread = ctx->spread;
+  sa.chunk = ctx->chunk;
 
   LaunchCfg c64;
   c64.waves = ctx->waves64;

@@ -110,6 +110,8 @@ struct SimArgs {
   int32_t path_f64;    // element type
   int32_t nslot;       // LDS slots per lane (max n)
   int32_t refill_min;  // refill a wave when at least this many lanes are idle
+  int32_t spread;      // FP32 pass: waves start spread over the buckets (1) or all in the largest (0)
+  int32_t chunk;       // items a wave claims with one atomic
 };
 
 }  // namespace links

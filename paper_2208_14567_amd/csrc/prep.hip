@@ -18,49 +18,70 @@ __device__ inline int popc(uint32_t x) { return __popc(x); }
 __device__ inline int lowbit(uint32_t x) { return __ffs(x) - 1; }
 __device__ inline uint32_t live_mask(int n) { return n >= 32 ? 0xFFFFFFFFu : ((1u << n) - 1u); }
 
-// squared distance written as (x_p - x_q)^2 + (y_p - y_q)^2, the reference's operation order
-__device__ inline double sqd(const double* p, const double* q) {
-  double dx = p[0] - q[0];
-  double dy = p[1] - q[1];
+constexpr int kPrepBlock = 128;   // solve-order kernel
+constexpr int kSortBlock = 64;    // count and fill kernels: one wave, rows staged in LDS
+
+// A candidate's adjacency rows and initial positions, read in place from global
+// memory (Global) or from the workgroup's LDS copy with the lanes interleaved
+// (Staged: element i of lane l at [i][l]).
+struct GlobalRow {
+  const uint32_t* adj;
+  const double* x0;
+  __device__ uint32_t a(int i) const { return adj[i]; }
+  __device__ double x(int i) const { return x0[2 * i]; }
+  __device__ double y(int i) const { return x0[2 * i + 1]; }
+};
+
+struct StagedRow {
+  const uint32_t* adj;  // &adj_l[0][lane]
+  const double* x0;     // &x0_l[0][lane]
+  __device__ uint32_t a(int i) const { return adj[i * kSortBlock]; }
+  __device__ double x(int i) const { return x0[(2 * i) * kSortBlock]; }
+  __device__ double y(int i) const { return x0[(2 * i + 1) * kSortBlock]; }
+};
+
+// squared distance written as (x_i - x_j)^2 + (y_i - y_j)^2, the reference's operation order
+template <typename Row>
+__device__ inline double sqd(const Row& r, int i, int j) {
+  const double dx = r.x(i) - r.x(j);
+  const double dy = r.y(i) - r.y(j);
   return dx * dx + dy * dy;
 }
 
-constexpr int kPrepBlock = 128;   // solve-order kernel
-constexpr int kSortBlock = 256;   // count and fill kernels (same blocking)
-
 // Integer structure of one candidate (the rules links_solve_order documents).
-__device__ bool structure_ok(int J, int n, const uint32_t* adj, uint32_t fixed, int pivot, int tip) {
+template <typename Row>
+__device__ bool structure_ok(int J, int n, const Row& r, uint32_t fixed, int pivot, int tip) {
   if (n < 3 || n > J) return false;
   const uint32_t live = live_mask(n);
   if (fixed & ~live) return false;
   for (int i = 0; i < J; i++) {
-    const uint32_t r = adj[i];
+    const uint32_t ri = r.a(i);
     if (i >= n) {
-      if (r) return false;
+      if (ri) return false;
       continue;
     }
-    if ((r & ~live) || ((r >> i) & 1u)) return false;
-    for (uint32_t m = r; m; m &= m - 1u)
-      if (!((adj[lowbit(m)] >> i) & 1u)) return false;
+    if ((ri & ~live) || ((ri >> i) & 1u)) return false;
+    for (uint32_t m = ri; m; m &= m - 1u)
+      if (!((r.a(lowbit(m)) >> i) & 1u)) return false;
   }
   if (pivot >= n || tip >= n || pivot == tip) return false;
-  if (!((fixed >> pivot) & 1u) || ((fixed >> tip) & 1u) || !((adj[pivot] >> tip) & 1u)) return false;
+  if (!((fixed >> pivot) & 1u) || ((fixed >> tip) & 1u) || !((r.a(pivot) >> tip) & 1u)) return false;
   return true;
 }
 
 // Finite positions and links longer than 1e-12; scale = longest link; counts the
 // links that are not between two fixed joints.
-__device__ bool geometry_ok(int n, const uint32_t* adj, uint32_t fixed, const double* x0, double* scale,
-                            int* movable_links) {
+template <typename Row>
+__device__ bool geometry_ok(int n, const Row& r, uint32_t fixed, double* scale, int* movable_links) {
   for (int i = 0; i < n; i++)
-    if (!isfinite(x0[2 * i]) || !isfinite(x0[2 * i + 1])) return false;
+    if (!isfinite(r.x(i)) || !isfinite(r.y(i))) return false;
   double sc = 0.0;
   int m = 0;
   bool ok = true;
   for (int i = 0; i < n; i++)
-    for (uint32_t r = adj[i] & ~((2u << i) - 1u); r; r &= r - 1u) {
-      const int j = lowbit(r);
-      const double L = sqrt(sqd(x0 + 2 * i, x0 + 2 * j));
+    for (uint32_t b = r.a(i) & ~((2u << i) - 1u); b; b &= b - 1u) {
+      const int j = lowbit(b);
+      const double L = sqrt(sqd(r, i, j));
       if (!(L > 1e-12)) ok = false;
       if (L > sc) sc = L;
       if (!(((fixed >> i) & 1u) && ((fixed >> j) & 1u))) m++;
@@ -73,7 +94,8 @@ __device__ bool geometry_ok(int n, const uint32_t* adj, uint32_t fixed, const do
 // Rounds of the graphical solver.  When ord != nullptr the entries are stored as
 // (k | a << 8 | b << 16) in ord[s * stride] and the entry index of joint k in
 // idx[k * stride].  Returns true when every joint is placed.
-__device__ bool solve_rounds(int n, const uint32_t* adj, uint32_t fixed, int tip, uint32_t* ord, uint8_t* idx,
+template <typename Row>
+__device__ bool solve_rounds(int n, const Row& r, uint32_t fixed, int tip, uint32_t* ord, uint8_t* idx,
                              int stride, int* nd_out, int* depth_out) {
   uint32_t known = fixed | (1u << tip);
   int nd = 0, depth = 0;
@@ -81,7 +103,7 @@ __device__ bool solve_rounds(int n, const uint32_t* adj, uint32_t fixed, int tip
     uint32_t now = 0u;
     for (int k = 0; k < n; k++) {
       if ((known >> k) & 1u) continue;
-      const uint32_t kn = adj[k] & known;
+      const uint32_t kn = r.a(k) & known;
       if (popc(kn) < 2) continue;
       if (ord) {
         const int a = lowbit(kn);
@@ -101,6 +123,32 @@ __device__ bool solve_rounds(int n, const uint32_t* adj, uint32_t fixed, int tip
   return known == live_mask(n);
 }
 
+// Copies the workgroup's adjacency rows and initial positions into LDS, lanes
+// interleaved, with coalesced loads (the rows of consecutive candidates are
+// contiguous in memory).  Every thread of the workgroup must call it.
+__device__ StagedRow stage_rows(const PrepArgs& A, unsigned char* smem) {
+  const int J = A.J;
+  const int tid = threadIdx.x;
+  const int c0 = blockIdx.x * kSortBlock;
+  const int nc = min(kSortBlock, A.B - c0);
+  uint32_t* adj_l = reinterpret_cast<uint32_t*>(smem);                          // [J][64]
+  double* x0_l = reinterpret_cast<double*>(smem + (size_t)J * kSortBlock * 4);  // [2J][64]
+  const uint32_t* ag = A.adj + (size_t)c0 * J;
+  const double2* xg = reinterpret_cast<const double2*>(A.x0 + (size_t)c0 * J * 2);
+  for (int e = tid; e < nc * J; e += kSortBlock) {
+    const int cand = e / J, i = e - cand * J;
+    adj_l[i * kSortBlock + cand] = ag[e];
+    const double2 v = xg[e];
+    x0_l[(2 * i) * kSortBlock + cand] = v.x;
+    x0_l[(2 * i + 1) * kSortBlock + cand] = v.y;
+  }
+  __syncthreads();
+  StagedRow r;
+  r.adj = adj_l + tid;
+  r.x0 = x0_l + tid;
+  return r;
+}
+
 __global__ void __launch_bounds__(kPrepBlock) solve_order_kernel(PrepArgs A) {
   __shared__ uint32_t ord_l[kMaxJ * kPrepBlock];
   __shared__ uint8_t idx_l[kMaxJ * kPrepBlock];
@@ -109,13 +157,15 @@ __global__ void __launch_bounds__(kPrepBlock) solve_order_kernel(PrepArgs A) {
   if (c >= A.B) return;
   const int J = A.J;
   const int n = A.n[c];
-  const uint32_t* adj = A.adj + (size_t)c * J;
+  GlobalRow row;
+  row.adj = A.adj + (size_t)c * J;
+  row.x0 = nullptr;
   const uint32_t fixed = A.fixed[c];
   const int pivot = A.motor[2 * c], tip = A.motor[2 * c + 1];
-  const bool ok = structure_ok(J, n, adj, fixed, pivot, tip);
+  const bool ok = structure_ok(J, n, row, fixed, pivot, tip);
   int nd = 0, depth = 0;
   bool complete = false;
-  if (ok) complete = solve_rounds(n, adj, fixed, tip, ord_l + tid, idx_l + tid, kPrepBlock, &nd, &depth);
+  if (ok) complete = solve_rounds(n, row, fixed, tip, ord_l + tid, idx_l + tid, kPrepBlock, &nd, &depth);
   if (A.order) {
     int8_t* o = A.order + (size_t)c * J * 3;
     for (int s = 0; s < J; s++) {
@@ -134,36 +184,37 @@ __global__ void __launch_bounds__(kPrepBlock) solve_order_kernel(PrepArgs A) {
 // ---- simulation set-up, pass 1: status of malformed / unsolvable candidates,
 // solve-order length D of the others and a per-workgroup histogram of D.
 __global__ void __launch_bounds__(kSortBlock) count_kernel(PrepArgs A) {
-  __shared__ int32_t hist[kMaxJ];
+  extern __shared__ unsigned char smem[];
+  const StagedRow row = stage_rows(A, smem);
   const int tid = threadIdx.x;
-  if (tid < kMaxJ) hist[tid] = 0;
-  __syncthreads();
-  const int c = blockIdx.x * blockDim.x + tid;
+  const int c = blockIdx.x * kSortBlock + tid;
+  int dl = 0xFF;
   if (c < A.B) {
     const int J = A.J;
     const int n = A.n[c];
-    const uint32_t* adj = A.adj + (size_t)c * J;
     const uint32_t fixed = A.fixed[c];
     const int pivot = A.motor[2 * c], tip = A.motor[2 * c + 1];
-    bool ok = structure_ok(J, n, adj, fixed, pivot, tip);
+    bool ok = structure_ok(J, n, row, fixed, pivot, tip);
     double scale = 0.0;
     int movable = 0;
-    if (ok) ok = geometry_ok(n, adj, fixed, A.x0 + (size_t)c * J * 2, &scale, &movable);
+    if (ok) ok = geometry_ok(n, row, fixed, &scale, &movable);
     int nd = 0, depth = 0;
     bool complete = false;
-    if (ok) complete = solve_rounds(n, adj, fixed, tip, nullptr, nullptr, 0, &nd, &depth);
+    if (ok) complete = solve_rounds(n, row, fixed, tip, (uint32_t*)nullptr, (uint8_t*)nullptr, 0, &nd, &depth);
     uint8_t st = !ok ? 5 : (complete ? kPending : 4);
     A.status[c] = st;
-    A.dlen[c] = st == kPending ? (uint8_t)nd : (uint8_t)0xFF;
+    dl = st == kPending ? nd : 0xFF;
+    A.dlen[c] = (uint8_t)dl;
     if (st != kPending) {
       A.fail_step[c] = -1;
       if (A.esc_step) A.esc_step[c] = -1;
-    } else {
-      atomicAdd(&hist[nd], 1);  // LDS: the counts do not depend on the order
     }
   }
-  __syncthreads();
-  if (tid < kMaxJ) A.block_hist[(size_t)blockIdx.x * kMaxJ + tid] = hist[tid];
+  // histogram of D over the workgroup (one wave)
+  for (int d = 0; d < kMaxJ; d++) {
+    const int k = __popcll(__ballot(dl == d));
+    if (tid == d) A.block_hist[(size_t)blockIdx.x * kMaxJ + d] = k;
+  }
 }
 
 // pass 2: exclusive scan of every bucket's per-workgroup counts (one workgroup per D)
@@ -207,41 +258,60 @@ __global__ void starts_kernel(int32_t* counters) {
 }
 
 // pass 3: position of every pending candidate in the sorted work list (largest D
-// first, candidate index within a bucket) and its records at that position.
-__global__ void __launch_bounds__(kSortBlock) fill_kernel(PrepArgs A) {
-  __shared__ uint32_t ord_l[kMaxJ * kSortBlock];
-  __shared__ uint8_t idx_l[kMaxJ * kSortBlock];
-  __shared__ int32_t wave_cnt[kSortBlock / kWave][kMaxJ];
+// first, candidate index within a bucket).
+__global__ void __launch_bounds__(kSortBlock) rank_kernel(PrepArgs A) {
   const int tid = threadIdx.x;
-  const int w = tid >> 6;
-  const int lane = tid & 63;
-  const int c = blockIdx.x * blockDim.x + tid;
+  const int c = blockIdx.x * kSortBlock + tid;
   const int myd = c < A.B ? A.dlen[c] : 0xFF;
-  // rank among the lanes of this wave with the same D, then among earlier waves
-  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  // rank among the lanes of this workgroup (one wave) with the same D
+  const uint64_t below = tid == 0 ? 0ull : (~0ull >> (64 - tid));
   int rank = 0;
   for (int d = 0; d < kMaxJ; d++) {
     const uint64_t m = __ballot(myd == d);
     if (myd == d) rank = __popcll(m & below);
-    if (lane == 0) wave_cnt[w][d] = __popcll(m);
   }
-  __syncthreads();
   if (myd == 0xFF) return;
-  for (int v = 0; v < w; v++) rank += wave_cnt[v][myd];
   const int p = A.counters[kCntOff + myd] + A.block_off[(size_t)blockIdx.x * kMaxJ + myd] + rank;
+  A.perm[p] = c;
+}
 
+// pass 4: the records of the candidate at every sorted position p.  Each lane
+// gathers its candidate's rows into its own LDS column, so the record writes of a
+// wave go to consecutive positions.
+__global__ void __launch_bounds__(kSortBlock) fill_kernel(PrepArgs A) {
+  extern __shared__ unsigned char smem[];
+  __shared__ uint32_t ord_l[kMaxJ * kSortBlock];
+  __shared__ uint8_t idx_l[kMaxJ * kSortBlock];
+  const int tid = threadIdx.x;
+  const int p = blockIdx.x * kSortBlock + tid;
+  if (p >= A.counters[kCntItems]) return;
+  const int c = A.perm[p];
   const int J = A.J;
-  const int Bs = A.Bs;
   const int n = A.n[c];
-  const uint32_t* adj = A.adj + (size_t)c * J;
+  StagedRow row;
+  {
+    uint32_t* adj_l = reinterpret_cast<uint32_t*>(smem);
+    double* x0_l = reinterpret_cast<double*>(smem + (size_t)J * kSortBlock * 4);
+    const uint32_t* ag = A.adj + (size_t)c * J;
+    for (int i = 0; i < J; i++) adj_l[i * kSortBlock + tid] = ag[i];
+    const double2* xg = reinterpret_cast<const double2*>(A.x0 + (size_t)c * J * 2);
+    for (int i = 0; i < n; i++) {
+      const double2 v = xg[i];
+      x0_l[(2 * i) * kSortBlock + tid] = v.x;
+      x0_l[(2 * i + 1) * kSortBlock + tid] = v.y;
+    }
+    row.adj = adj_l + tid;
+    row.x0 = x0_l + tid;
+  }
+
+  const int Bs = A.Bs;
   const uint32_t fixed = A.fixed[c];
   const int pivot = A.motor[2 * c], tip = A.motor[2 * c + 1];
-  const double* x0 = A.x0 + (size_t)c * J * 2;
   int nd = 0, depth = 0;
-  solve_rounds(n, adj, fixed, tip, ord_l + tid, idx_l + tid, kSortBlock, &nd, &depth);
+  solve_rounds(n, row, fixed, tip, ord_l + tid, idx_l + tid, kSortBlock, &nd, &depth);
   double scale = 0.0;
   int movable = 0;
-  geometry_ok(n, adj, fixed, x0, &scale, &movable);
+  geometry_ok(n, row, fixed, &scale, &movable);
   const int D = nd;
   // links outside the solve order: all but the actuator arm and two per placed joint
   const int redundant = movable - 1 - 2 * nd;
@@ -266,8 +336,8 @@ __global__ void __launch_bounds__(kSortBlock) fill_kernel(PrepArgs A) {
   A.meta[p] = m;
   A.perm[p] = c;
 
-  const double px = x0[2 * pivot], py = x0[2 * pivot + 1];
-  const double vx = x0[2 * tip] - px, vy = x0[2 * tip + 1] - py;
+  const double px = row.x(pivot), py = row.y(pivot);
+  const double vx = row.x(tip) - px, vy = row.y(tip) - py;
   const double scale2 = scale * scale;
   CandF64 cd;
   cd.px = px;
@@ -302,8 +372,8 @@ __global__ void __launch_bounds__(kSortBlock) fill_kernel(PrepArgs A) {
   for (int s = 0; s < D; s++) {
     const uint32_t e = ord_l[s * kSortBlock + tid];
     const int k = e & 0xFF, a = (e >> 8) & 0xFF, b = (e >> 16) & 0xFF;
-    const double ra2 = sqd(x0 + 2 * k, x0 + 2 * a);
-    const double rb2 = sqd(x0 + 2 * k, x0 + 2 * b);
+    const double ra2 = sqd(row, k, a);
+    const double rb2 = sqd(row, k, b);
     const double ra = sqrt(ra2), rb = sqrt(rb2);
     const double sum = ra + rb, dif = ra - rb;
     DyadF64 q;
@@ -321,7 +391,7 @@ __global__ void __launch_bounds__(kSortBlock) fill_kernel(PrepArgs A) {
   }
   for (int j = 0; j < n; j++) {
     const int sl = slot_of(j);
-    A.x0s[(size_t)sl * Bs + p] = make_float2((float)x0[2 * j], (float)x0[2 * j + 1]);
+    A.x0s[(size_t)sl * Bs + p] = make_float2((float)row.x(j), (float)row.y(j));
     A.slot_joint[(size_t)sl * Bs + p] = (uint8_t)j;
   }
 }
@@ -446,9 +516,12 @@ hipError_t launch_solve_order(const PrepArgs& a, hipStream_t st) {
 
 int prep_blocks(int32_t B) { return (B + kSortBlock - 1) / kSortBlock; }
 
+// LDS of the staged rows: adjacency [J][64] u32 and positions [2J][64] f64
+size_t staged_bytes(int J) { return (size_t)J * kSortBlock * (4 + 16); }
+
 hipError_t launch_prep_count(const PrepArgs& a, hipStream_t st) {
   if (a.B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(count_kernel, dim3(prep_blocks(a.B)), dim3(kSortBlock), 0, st, a);
+  hipLaunchKernelGGL(count_kernel, dim3(prep_blocks(a.B)), dim3(kSortBlock), staged_bytes(a.J), st, a);
   return hipGetLastError();
 }
 
@@ -462,7 +535,8 @@ hipError_t launch_prep_offsets(const PrepArgs& a, hipStream_t st) {
 
 hipError_t launch_prep_fill(const PrepArgs& a, hipStream_t st) {
   if (a.B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_kernel, dim3(prep_blocks(a.B)), dim3(kSortBlock), 0, st, a);
+  hipLaunchKernelGGL(rank_kernel, dim3(prep_blocks(a.B)), dim3(kSortBlock), 0, st, a);
+  hipLaunchKernelGGL(fill_kernel, dim3(prep_blocks(a.B)), dim3(kSortBlock), staged_bytes(a.J), st, a);
   return hipGetLastError();
 }
 

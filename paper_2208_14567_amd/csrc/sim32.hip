@@ -26,6 +26,12 @@ __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x);
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// a non-negative FP32 bound rounded up to 16 bits (upper half of its encoding)
+__device__ __forceinline__ uint16_t bound_up(float e) {
+  return (uint16_t)((__float_as_uint(e) + 0xFFFFu) >> 16);
+}
+__device__ __forceinline__ float bound_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
 __device__ __forceinline__ int mbcnt64(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
@@ -37,7 +43,9 @@ sim32_kernel(SimArgs A) {
   const int bd = blockDim.x;
   const int tid = threadIdx.x;
   float2* P = reinterpret_cast<float2*>(smem);  // [nslot][bd]
-  float* E = reinterpret_cast<float*>(P + (size_t)A.nslot * bd);
+  // error bounds, stored as the upper 16 bits of the FP32 value rounded up (a
+  // bound that is at most 0.4% larger, so it stays a bound)
+  uint16_t* E = reinterpret_cast<uint16_t*>(P + (size_t)A.nslot * bd);
   const int T = A.T;
   const int J = A.J;
   // crank table (cos, sin) of every step: in LDS when it fits, so that the step
@@ -72,25 +80,30 @@ sim32_kernel(SimArgs A) {
   // the lanes of a wave place the same number of joints per step; an exhausted
   // bucket sends the wave on to the next smaller bucket that still has work.
   const int* cnt = A.counters;
+  const int nwaves = gridDim.x * (blockDim.x / kWave);
   int bucket = 0;
   uint32_t done_mask = 0u;  // buckets this wave has seen exhausted (wave-uniform)
   {
-    const int nw = gridDim.x * (blockDim.x / kWave);
+    const int nw = nwaves;
     const int gw = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
     const long long items = cnt[kCntItems];
-    const long long target = (2LL * gw + 1) * items / (2LL * nw);
+    const long long target = A.spread ? (2LL * gw + 1) * items / (2LL * nw) : 0LL;
     for (int d = kMaxJ - 1; d >= 0; d--) {
       if (cnt[kCntHist + d] == 0) done_mask |= 1u << d;
       else if (cnt[kCntOff + d] <= target) bucket = d;
     }
   }
-  // Work is claimed one refill ahead: the atomic claim issued at a refill is only
-  // read at the next one, so its latency hides behind the steps in between.
-  int pre_raw = 0;        // the claim's return value (meaningful in lane 0)
+  // Work is claimed in chunks of A.chunk items held by the wave (one atomic per
+  // chunk, not per refill), and the next chunk is claimed ahead: the atomic is
+  // issued after a refill's record loads and read only when the wave's current
+  // range runs out, so its latency hides behind the steps in between.
+  int pre_raw = 0;        // the pending claim's return value (meaningful in lane 0)
   bool pre_pending = false;
   int pre_bucket = 0, pre_req = 0;
-  int pre_base = 0, pre_left = 0;  // claimed items not yet handed to lanes
+  int pre_base = 0, pre_left = 0;    // current range: claimed items not yet handed to lanes
+  int next_base = 0, next_left = 0;  // the range after it (from a resolved claim)
   const int rm = A.refill_min;
+  const int chunk = A.chunk;
 
   // next bucket that may still have work: smaller ones first, then larger ones
   auto pick_bucket = [&]() -> bool {
@@ -125,26 +138,34 @@ sim32_kernel(SimArgs A) {
     if (nidle == kWave && exhausted) break;
     if (!exhausted && nidle > 0 && (nidle >= rm || nidle == kWave)) {
       int p = -1;
-      // the claim made at the previous refill
-      if (pre_pending) {
-        const int base = __shfl(pre_raw, 0);
-        const int end = cnt[kCntOff + pre_bucket] + cnt[kCntHist + pre_bucket];
-        const int got = min(max(end - base, 0), pre_req);
-        if (got < pre_req) done_mask |= 1u << pre_bucket;
-        pre_base = base;
-        pre_left = got;
-        pre_pending = false;
-      }
-      if (pre_left > 0) {
-        const int m = min(nidle, pre_left);
-        if (cand < 0) {
-          const int r = mbcnt64(idle);
-          if (r < m) p = pre_base + r;
+      // hand out the wave's claimed ranges: the current one, then the next one
+      // (resolving the claim made ahead when the current range cannot cover)
+      for (int k = 0; k < 2 && nidle > 0; ++k) {
+        if (pre_left == 0 && next_left == 0 && pre_pending) {
+          const int base = __shfl(pre_raw, 0);
+          const int end = cnt[kCntOff + pre_bucket] + cnt[kCntHist + pre_bucket];
+          const int got = min(max(end - base, 0), pre_req);
+          if (got < pre_req) done_mask |= 1u << pre_bucket;
+          next_base = base;
+          next_left = got;
+          pre_pending = false;
         }
-        pre_base += m;
-        pre_left -= m;
-        idle = __ballot(cand < 0 && p < 0);
-        nidle = __popcll(idle);
+        if (pre_left == 0) {
+          pre_base = next_base;
+          pre_left = next_left;
+          next_left = 0;
+        }
+        if (pre_left > 0) {
+          const int m = min(nidle, pre_left);
+          if (cand < 0 && p < 0) {
+            const int r = mbcnt64(idle);
+            if (r < m) p = pre_base + r;
+          }
+          pre_base += m;
+          pre_left -= m;
+          idle = __ballot(cand < 0 && p < 0);
+          nidle = __popcll(idle);
+        }
       }
       // the rest now; every failed claim marks its bucket done, so this ends
       // within 33 attempts
@@ -204,17 +225,34 @@ sim32_kernel(SimArgs A) {
                 cSl[s >> 1] = q.slots & 0xFFFFu;
             }
           }
-          for (int sl = 0; sl < n; ++sl) {
-            const float2 q = A.x0s[(size_t)sl * Bs + p];
-            P[sl * bd + tid] = q;
-            E[sl * bd + tid] = uu * (fabsf(q.x) + fabsf(q.y));  // rounding of x0 to FP32
+          // initial positions, a group of slots at a time with the group's loads
+          // issued together
+          constexpr int NMAX = DMAX + 2;  // joints per candidate at most (J of this template)
+          constexpr int G = 4;
+#pragma unroll
+          for (int g = 0; g < NMAX; g += G) {
+            float2 xq[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k)
+              if (g + k < n) xq[k] = A.x0s[(size_t)(g + k) * Bs + p];
+#pragma unroll
+            for (int k = 0; k < G; ++k)
+              if (g + k < n) {
+                P[(g + k) * bd + tid] = xq[k];
+                E[(g + k) * bd + tid] = bound_up(uu * (fabsf(xq[k].x) + fabsf(xq[k].y)));  // rounding of x0 to FP32
+              }
           }
         }
       }
-      // claim the next refill's work ahead of time, after the record loads so
-      // that nothing waits on it before the next refill
-      if (!exhausted && pre_left == 0 && !((done_mask >> bucket) & 1u)) {
-        pre_req = max(rm, 1);
+      // claim the next chunk ahead of time, after the record loads so that
+      // nothing waits on it before the current range runs out
+      if (!exhausted && !pre_pending && next_left == 0 && pre_left < chunk && !((done_mask >> bucket) & 1u)) {
+        // guided size: a share of what remains in the bucket after the current
+        // range, split over the waves that work on it, between rm and chunk
+        const int end = cnt[kCntOff + bucket] + cnt[kCntHist + bucket];
+        const long long wb = max(1LL, (long long)nwaves * cnt[kCntHist + bucket] / max(cnt[kCntItems], 1));
+        const int share = (int)((long long)max(end - (pre_base + pre_left), 0) / wb);
+        pre_req = min(chunk, max(share, max(rm, 1)));
         pre_bucket = bucket;
         if (lane_id() == 0) pre_raw = atomicAdd(&A.counters[kCntCur + bucket], pre_req);
         pre_pending = true;
@@ -237,7 +275,7 @@ sim32_kernel(SimArgs A) {
     const float tx = fmaf(cs.x, vx, fmaf(-cs.y, vy, px));
     const float ty = fmaf(cs.y, vx, fmaf(cs.x, vy, py));
     P[D * bd + tid] = make_float2(tx, ty);
-    E[D * bd + tid] = U;
+    E[D * bd + tid] = bound_up(U);
 
     bool ev = force64, lock_ev = false;
     int lock_kind = 1;
@@ -274,9 +312,9 @@ sim32_kernel(SimArgs A) {
       float Ek = 0.f, Ep = 0.f;
       if ((MODE & 1) == 0) {
         // error bound of the parents and of this placement
-        const float Ea = E[a * bd + tid];
-        const float Eb = E[b * bd + tid];
-        Ep = E[s * bd + tid];
+        const float Ea = bound_f(E[a * bd + tid]);
+        const float Eb = bound_f(E[b * bd + tid]);
+        Ep = bound_f(E[s * bd + tid]);
         const float Eab = Ea + Eb;
         const float d = d2 * rd;
         const float h = 0.5f * sK * rd;
@@ -299,7 +337,7 @@ sim32_kernel(SimArgs A) {
         write = act & !deg & !lock;
       }
       P[s * bd + tid] = write ? make_float2(nx, ny) : pr;
-      if ((MODE & 1) == 0) E[s * bd + tid] = write ? Ek : Ep;
+      if ((MODE & 1) == 0) E[s * bd + tid] = bound_up(write ? Ek : Ep);
       }
     }
 
@@ -372,7 +410,7 @@ int sim32_dmax(int J) {
 }
 
 int sim32_lds_bytes(int nslot, int waves, int T) {
-  return nslot * waves * kWave * (int)(sizeof(float2) + sizeof(float)) +
+  return nslot * waves * kWave * (int)(sizeof(float2) + sizeof(uint16_t)) +
          (T <= kTableLds ? T * (int)sizeof(float2) : 0);
 }
 

@@ -115,21 +115,55 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
     cSl[s] = 0u;
   }
 
+  // Work is claimed in chunks of A.chunk list entries per atomic; the next chunk
+  // is claimed ahead (after a refill's loads) and read when the current range
+  // runs out.
+  const int chunk = A.chunk;
+  int cur_base = 0, cur_left = 0;   // entries claimed and not yet handed to lanes
+  int pre_raw = 0, pre_req = 0;     // pending claim (return value meaningful in lane 0)
+  bool pre_pending = false;
+  const int nwaves = gridDim.x * (blockDim.x / kWave);
+  bool no_more = false;             // a claim of this wave reached the end of the list
   for (;;) {
-    const uint64_t idle = __ballot(cand < 0);
-    const int nidle = __popcll(idle);
+    uint64_t idle = __ballot(cand < 0);
+    int nidle = __popcll(idle);
     if (nidle == kWave && exhausted) break;
-    // idle lanes wait until enough of them can be refilled with one claim
+    // idle lanes wait until enough of them can be refilled
     if (!exhausted && nidle > 0 && (nidle >= A.refill_min || nidle == kWave)) {
-      const int leader = __ffsll((unsigned long long)idle) - 1;
-      int base = 0;
-      if (__lane_id() == leader) base = atomicAdd(&A.counters[cnt_next], nidle);
-      base = __shfl(base, leader);
       const int items = A.counters[cnt_items];
-      if (base + nidle >= items) exhausted = true;
+      int p = -1;
+      for (int k = 0; k < 3 && nidle > 0; ++k) {
+        if (cur_left == 0) {
+          int base = 0, req = chunk;
+          if (pre_pending) {
+            base = __shfl(pre_raw, 0);
+            req = pre_req;
+            pre_pending = false;
+          } else if (!no_more) {
+            const int cur = __hip_atomic_load(&A.counters[cnt_next], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            req = min(chunk, max(nidle, max(items - cur, 0) / nwaves));
+            if (__lane_id() == 0) base = atomicAdd(&A.counters[cnt_next], req);
+            base = __shfl(base, 0);
+          } else {
+            break;
+          }
+          cur_base = base;
+          cur_left = min(max(items - base, 0), req);
+          if (base + req >= items) no_more = true;
+        }
+        const int m = min(nidle, cur_left);
+        if (cand < 0 && p < 0) {
+          const int r = mbcnt64(idle);
+          if (r < m) p = cur_base + r;
+        }
+        cur_base += m;
+        cur_left -= m;
+        idle = __ballot(cand < 0 && p < 0);
+        nidle = __popcll(idle);
+      }
+      exhausted = no_more && cur_left == 0 && !pre_pending;
       if (cand < 0) {
-        const int p = base + mbcnt64(idle);
-        if (p < items) {
+        if (p >= 0) {
           int it;
           int t0 = 0;
           bool from_x0 = true;
@@ -183,21 +217,53 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
                 cSl[s] = A.df[(size_t)s * Bs + it].slots;
               }
             }
-            const double* x0 = A.x0 + (size_t)c * J * 2;
+            const double2* x0 = reinterpret_cast<const double2*>(A.x0 + (size_t)c * J * 2);
             const float2* dump = SRC == kFromEsc ? A.esc_pos + (size_t)p * J : nullptr;
-            for (int sl = 0; sl < n; ++sl) {
-              double2 v;
-              if (sl > D || from_x0) {  // fixed joints, or reference positions at t = 0
-                const int j = A.slot_joint[(size_t)sl * Bs + it];
-                v = make_double2(x0[2 * j], x0[2 * j + 1]);
-              } else {
-                const float2 q = dump[sl];
-                v = make_double2((double)q.x, (double)q.y);
+            // initial positions, four slots at a time: the slot -> joint maps of
+            // the group, then its positions, each set of loads issued together
+            constexpr int NMAX = DMAX + 2;  // joints per candidate at most (J of this template)
+            constexpr int G = 4;
+#pragma unroll
+            for (int g = 0; g < NMAX; g += G) {
+              int jq[G];
+#pragma unroll
+              for (int k = 0; k < G; ++k) {
+                const int sl = g + k;
+                jq[k] = 0;
+                if (sl < n && (sl > D || from_x0)) jq[k] = A.slot_joint[(size_t)sl * Bs + it];
               }
-              P[sl * bd + tid] = v;
+              double qx[G], qy[G];
+#pragma unroll
+              for (int k = 0; k < G; ++k) {
+                const int sl = g + k;
+                qx[k] = 0.0;
+                qy[k] = 0.0;
+                if (sl < n) {
+                  if (sl > D || from_x0) {  // fixed joints, or reference positions at t = 0
+                    const double2 q = x0[jq[k]];
+                    qx[k] = q.x;
+                    qy[k] = q.y;
+                  } else {
+                    const float2 q = dump[sl];
+                    qx[k] = (double)q.x;
+                    qy[k] = (double)q.y;
+                  }
+                }
+              }
+#pragma unroll
+              for (int k = 0; k < G; ++k)
+                if (g + k < n) P[(g + k) * bd + tid] = make_double2(qx[k], qy[k]);
             }
           }
         }
+      }
+      // claim the next chunk ahead, after this refill's loads; guided size: the
+      // waves' share of what remains after the current range, at most chunk
+      if (!pre_pending && !no_more && cur_left < chunk) {
+        const int share = max(items - (cur_base + cur_left), 0) / nwaves;
+        pre_req = min(chunk, max(share, max(A.refill_min, 1)));
+        if (__lane_id() == 0) pre_raw = atomicAdd(&A.counters[cnt_next], pre_req);
+        pre_pending = true;
       }
     }
     if (cand >= 0) {

@@ -47,7 +47,7 @@ class SimOut(ctypes.Structure):
 EXPORTS = ["links_create", "links_destroy", "links_last_error", "links_version", "links_solve_order",
            "links_sim_opts_default", "links_simulate", "links_normalize_paths", "links_set_tuning",
            "links_get_tuning", "links_set_option", "links_normalize_paths_n", "links_profile", "links_last_timings",
-           "links_graph_create", "links_graph_launch", "links_graph_destroy"]
+           "links_graph_create", "links_graph_launch", "links_graph_destroy", "links_get_option"]
 TIMING_PASSES = ["prep_count", "prep_fill", "fp32_pass", "fp64_pass", "compaction", "path_pass"]
 
 _lib = None
@@ -84,6 +84,8 @@ def load() -> ctypes.CDLL:
     L.links_get_tuning.restype = ctypes.c_int
     L.links_set_option.argtypes = [P, ctypes.c_char_p, ctypes.c_int]
     L.links_set_option.restype = ctypes.c_int
+    L.links_get_option.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)]
+    L.links_get_option.restype = ctypes.c_int
     L.links_normalize_paths_n.argtypes = [P, P, P, i32, i32, i32, P, P, P]
     L.links_normalize_paths_n.restype = ctypes.c_int
     L.links_profile.argtypes = [P, ctypes.c_int]
@@ -182,6 +184,11 @@ class Context:
 
     def set_option(self, name: str, value: int):
         _check(load().links_set_option(self._h, name.encode(), int(value)), "links_set_option")
+
+    def get_option(self, name: str) -> int:
+        v = ctypes.c_int()
+        _check(load().links_get_option(self._h, name.encode(), ctypes.byref(v)), "links_get_option")
+        return v.value
 
     def get_tuning(self) -> dict:
         v = [ctypes.c_int() for _ in range(5)]

@@ -144,6 +144,18 @@ def test_fp32_recheck_parity(ctx, L, name, B, seed):
     _fp32_parity(ctx, L, b, label=name)
 
 
+def test_fp32_recheck_parity_exact_handover(ctx, L):
+    """The same bar with the hand-over pass evaluating the correctly rounded FP64
+    sequence instead of reciprocal square roots with Newton steps."""
+    _say("[fp32r exact hand-over]")
+    b = gen.workload("dyad_6_20", 20000, seed=12)
+    ctx.set_option("exact_handover", 1)
+    try:
+        _fp32_parity(ctx, L, b, label="exact hand-over")
+    finally:
+        ctx.set_option("exact_handover", 0)
+
+
 @pytest.mark.parametrize("T", [1, 2, 50, 333])
 def test_step_counts(ctx, L, T):
     _say(f"[T] {T}")
@@ -198,15 +210,20 @@ def test_deterministic_across_tunings(ctx, L):
     b = gen.workload("dyad_skewed", 30000, seed=31)
     db = L.to_device(b)
     base = _np(ctx.simulate(db, write=L.WRITE_ALL))
+    saved = ctx.get_tuning()
     try:
-        for w32, rmin, w64 in ((1, 1, 1), (4, 32, 2), (2, 64, 4), (1, 8, 1)):
+        for w32, rmin, w64, spread, r64 in ((1, 1, 1, 1, 1), (4, 32, 2, 0, 8), (2, 64, 4, 1, 64), (1, 8, 1, 0, 32)):
             ctx.set_tuning(w32, rmin, w64)
+            ctx.set_option("spread", spread)
+            ctx.set_option("refill64", r64)
             r = _np(ctx.simulate(db, write=L.WRITE_ALL))
             for k in ("status", "fail_step", "esc_step"):
-                assert np.array_equal(r[k], base[k]), (k, w32, rmin, w64)
+                assert np.array_equal(r[k], base[k]), (k, w32, rmin, w64, spread, r64)
             assert np.array_equal(np.nan_to_num(r["path"], nan=7.0), np.nan_to_num(base["path"], nan=7.0))
     finally:
-        ctx.set_tuning(1, 8, 1)
+        ctx.set_tuning(saved["waves32"], saved["refill_min"], saved["waves64"])
+        ctx.set_option("spread", 1)
+        ctx.set_option("refill64", 32)
     # a candidate gives the same result alone and in the mix
     for c in (0, 17, 4242):
         one = _np(ctx.simulate(L.to_device(b.take([c])), write=L.WRITE_ALL))

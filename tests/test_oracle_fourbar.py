@@ -161,3 +161,33 @@ def test_grashof_full_rotation(oracle_lib):
             assert not valid[c]
             checked += 1
     assert checked > 100
+
+
+def test_discriminant_and_distance_margins_closed_form(oracle_lib):
+    """The band margins the oracle reports (used to split candidates into
+    decided-outside-the-band and in-band) against closed forms for crank-rocker
+    four-bars: joint 3 hangs between the crank tip 1 and pivot 2, so its parent
+    distance is |p1(t) - x0_2| and its discriminant the Heron product of the two
+    link lengths and that distance; the coupler joint 4 sits on the rigid triangle
+    1-3-4, whose parent distance and discriminant never change."""
+    T = 200
+    b = gen.workload("fourbar", 300, seed=51)
+    r = oracle.simulate(b, T=T, margins=True)
+    assert np.all(r["status"] == oracle.VALID)
+    t = np.arange(T)
+    for c in range(b.B):
+        x0 = b.x0[c]
+        L = lambda i, j: float(np.hypot(*(x0[i] - x0[j])))
+        scale = max(L(0, 1), L(1, 3), L(2, 3), L(1, 4), L(3, 4))
+        p1 = complex(*x0[0]) + complex(*(x0[1] - x0[0])) * np.exp(2j * np.pi * t / T)
+        d3 = np.abs(p1 - complex(*x0[2]))
+        ra, rb = L(1, 3), L(2, 3)
+        K3 = ((ra + rb) ** 2 - d3 ** 2) * (d3 ** 2 - (ra - rb) ** 2)
+        ra4, rb4, d4 = L(1, 4), L(3, 4), L(1, 3)
+        K4 = ((ra4 + rb4) ** 2 - d4 ** 2) * (d4 ** 2 - (ra4 - rb4) ** 2)
+        want_disc = min(np.abs(K3).min(), abs(K4)) / (4 * scale ** 4)
+        want_deg = min((d3 ** 2).min(), d4 ** 2) / scale ** 2
+        m = r["margins"][c]
+        assert abs(m[0] - want_disc) <= 1e-9 * max(want_disc, 1e-12), (c, m[0], want_disc)
+        assert abs(m[1] - want_deg) <= 1e-9 * want_deg, (c, m[1], want_deg)
+        assert np.isinf(m[3])   # no redundant link, no drift check
