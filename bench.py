@@ -163,6 +163,114 @@ def end_to_end(L, ctx, host, dev, T):
     return res
 
 
+def time_sim(ctx, db, reps, warmup=2, **kw):
+    """Mean wall time of links_simulate (HIP events around each pass) and the
+    per-pass means."""
+    import torch
+    for _ in range(warmup):
+        ctx.simulate(db, **kw)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    passes = []
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = ctx.simulate(db, **kw)
+        passes.append(ctx.last_timings())
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    ctx.profile(False)
+    return dt, {k: float(np.mean([p[k] for p in passes])) for k in passes[0]}, r
+
+
+def other_config(args, L, gen):
+    """Secondary configurations (their own JSON line; not the headline)."""
+    import torch
+    import oracle
+    from paper_2208_14567_amd import tune
+    dev = torch.device("cuda:0")
+    T = args.T
+    threads = min(os.cpu_count() or 1, 64)
+    if args.config == "cfg1":
+        host = gen.workload("fourbar", 10_000, seed=1)
+        db = L.to_device(host, dev)
+        ctx = L.Context(0)
+        t0 = time.perf_counter()
+        ref = oracle.simulate(host, T=T, path=True, margins=True, nthreads=threads)
+        t_or = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.simulate(host.slice(0, 2000), T=T, nthreads=1)
+        t_or1 = (time.perf_counter() - t0) * host.B / 2000
+        res = {"metric": "four-bar sims/sec (200 steps)", "unit": "sims/s", "config": {
+            "workload": "10,000 Grashof crank-rocker four-bars with a coupler point, x0~U[0,1)^2, T=200",
+            "candidates": host.B, "T": T, "seed": 1}}
+        for name, prec in (("gpu_fp64", L.FP64), ("gpu_fp32_recheck", L.FP32_RECHECK)):
+            dt, passes, r = time_sim(ctx, db, reps=20, T=T, precision=prec, write=L.WRITE_ALL,
+                                     path_dtype=L.F64 if prec == L.FP64 else L.F32)
+            st = r["status"].cpu().numpy()
+            fs = r["fail_step"].cpu().numpy()
+            path = r["path"].cpu().numpy().astype(np.float64)
+            scale = np.array([max(np.hypot(*(host.x0[c, i] - host.x0[c, j]))
+                                  for i in range(5) for j in range(i + 1, 5) if (host.adj[c, i] >> j) & 1)
+                              for c in range(host.B)])
+            ok = (st == ref["status"]) & (fs == ref["fail_step"])
+            err = np.nanmax(np.abs(path - ref["path"]), axis=(1, 2)) / scale
+            res[name] = {"value": host.B / dt, "ms": dt * 1e3, "passes_ms": passes,
+                         "status_equal": float(ok.mean()), "max_path_error_over_scale": float(np.nanmax(err)),
+                         "bit_exact_paths": bool(np.array_equal(np.nan_to_num(path, nan=7.0),
+                                                                np.nan_to_num(ref["path"], nan=7.0)))}
+        res["value"] = res["gpu_fp32_recheck"]["value"]
+        res["valid_fraction"] = float((ref["status"] == 0).mean())
+        res["cpu_oracle"] = {"value": host.B / t_or, "cores": threads, "one_core": host.B / t_or1}
+        return res
+    if args.config == "cfg1x":
+        B = 10_000_000
+        host = gen.workload("fourbar_u", B, seed=11)
+        db = L.to_device(host, dev)
+        ctx = L.Context(0)
+        path = torch.empty((B, T, 2), dtype=torch.float32, device=dev)
+        dt, passes, r = time_sim(ctx, db, reps=5, T=T, precision=L.FP32_RECHECK, write=L.WRITE_ALL,
+                                 out={"path": path})
+        wbytes = B * T * 8
+        pp = passes["path_pass"] * 1e-3
+        return {"metric": "four-bar sims/sec writing every coupler path", "unit": "sims/s", "value": B / dt,
+                "ms_per_step": dt * 1e3, "passes_ms": passes,
+                "config": {"workload": "10M four-bars, x0~U[0,1)^2 (no rejection), T=200, every path written "
+                                       "(NaN after a lock)", "candidates": B, "T": T, "seed": 11},
+                "roofline": {"bound": "hbm", "kernel": "sim64_kernel path pass", "achieved": wbytes / pp / 1e9,
+                             "peak": 8000.0, "unit": "GB/s", "frac": wbytes / pp / 8e12,
+                             "bytes_per_launch": wbytes}}
+    # cfg3: 4M skewed joint counts, autotuned
+    B = 4_000_000
+    host = gen.workload("dyad_skewed", B, seed=3)
+    db = L.to_device(host, dev)
+    ctx = L.Context(0)
+    tuned = tune.autotune(ctx, db, T=T, precision=L.FP32_RECHECK, use_cache=False)
+    dt, passes, r = time_sim(ctx, db, reps=10, T=T, precision=L.FP32_RECHECK)
+    st = r["status"].cpu().numpy()
+    ctx64 = L.Context(0)
+    tuned64 = tune.autotune(ctx64, db, T=T, precision=L.FP64, use_cache=False,
+                            space={"chunk": tune.SPACE["chunk"], "refill64": [1, 8, 32]})
+    dt64, passes64, r64 = time_sim(ctx64, db, reps=10, T=T, precision=L.FP64)
+    # parity on a sample the oracle computes
+    idx = np.random.default_rng(0).choice(B, 20000, replace=False)
+    ref = oracle.simulate(host.take(idx), T=T, margins=True, nthreads=threads)
+    clear = ~oracle.in_band(ref["margins"])
+    fs = r["fail_step"].cpu().numpy()
+    agree = (st[idx] == ref["status"]) & (fs[idx] == ref["fail_step"])
+    return {"metric": "mechanism sims/sec (200 steps), skewed joint counts", "unit": "sims/s", "value": B / dt,
+            "ms_per_step": dt * 1e3, "passes_ms": passes, "tuning": tuned["config"],
+            "config": {"workload": "4M dyad-built candidates, n: 60% U{6..8}, 30% U{9..14}, 10% U{15..20}, "
+                                   "x0~U[0,1)^2, T=200, FP32 with FP64 escalation", "candidates": B, "T": T,
+                       "seed": 3},
+            "fp64_plain": {"value": B / dt64, "ms_per_step": dt64 * 1e3, "passes_ms": passes64,
+                           "tuning": tuned64["config"]},
+            "valid_fraction": float((st == 0).mean()),
+            "escalated_fraction": float((r["esc_step"].cpu().numpy() >= 0).mean()),
+            "sample_parity": {"sample": int(idx.size), "out_of_band": int(clear.sum()),
+                              "out_of_band_equal": float(agree[clear].mean()),
+                              "in_band_equal": float(agree[~clear].mean()) if (~clear).any() else None}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,6 +285,10 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch parameters")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--config", choices=["cfg2", "cfg1", "cfg1x", "cfg3"], default="cfg2",
+                    help="cfg2: the headline (1M dyad-built, 6-20 joints); cfg1: 10k crank-rocker four-bars "
+                         "(oracle, GPU FP64, GPU FP32+recheck); cfg1x: 10M four-bars writing every path "
+                         "(HBM-write roofline); cfg3: 4M skewed joint counts")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device (HBM traffic scale for counters)")
     args = ap.parse_args()
@@ -187,6 +299,9 @@ def main():
     import torch
     from paper_2208_14567_amd import gen, links as L
 
+    if args.config != "cfg2":
+        print(json.dumps(other_config(args, L, gen)))
+        return
     dev = torch.device("cuda:0")
     B, T = args.B, args.T
     t0 = time.time()

@@ -98,7 +98,11 @@ const char* links_version(void);
  *   adj   uint32 [B][J]    bit j of adj[c][i] set iff joints i and j are linked
  *   fixed uint32 [B]       bit i set iff joint i is a ground (fixed) joint
  *   motor uint8  [B][2]    (pivot, tip): pivot fixed, tip free, link pivot-tip present
- *   x0    double [B][J][2] initial positions; entries beyond n are ignored       */
+ *   x0    double [B][J][2] initial positions; entries beyond n are ignored
+ *   x0_f32 float  [B][J][2] the same in single precision, used when x0 is NULL
+ *                          (the values are widened to double exactly, so results
+ *                          equal those of x0 holding the same numbers); exactly
+ *                          one of x0 and x0_f32 must be non-NULL when B > 0      */
 typedef struct {
   int32_t B, J;
   const uint8_t* n;
@@ -106,6 +110,7 @@ typedef struct {
   const uint32_t* fixed;
   const uint8_t* motor;
   const double* x0;
+  const float* x0_f32;
 } links_batch;
 
 /* Graphical solve order (Methodology, "Graphical Simulator"): starting from the

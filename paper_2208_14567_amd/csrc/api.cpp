@@ -47,8 +47,8 @@ struct links_ctx {
   std::map<std::string, Buf> bufs;
   std::map<int, bool> tables;  // crank tables uploaded, by T
   // launch parameters (see links_set_tuning)
-  int waves32 = 1;
-  int refill_min = 48;
+  int waves32 = 4;
+  int refill_min = 32;
   int waves64 = 1;
   int refill64 = 32;           // refill threshold of the FP64 passes
   int spread = 1;              // FP32 waves start spread over the solve-order buckets
@@ -334,7 +334,9 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
     return fail(LINKS_ERR_ARG, "out_joint %d outside [-1, J)", opts->out_joint);
   if (!(opts->eps_disc >= 0) || !(opts->eps_branch >= 0) || !(opts->tau_drift >= 0))
     return fail(LINKS_ERR_ARG, "negative or NaN tolerance");
-  if (B > 0 && (!batch->x0 || !out->status)) return fail(LINKS_ERR_ARG, "x0 or status is NULL");
+  if (B > 0 && !out->status) return fail(LINKS_ERR_ARG, "status is NULL");
+  if (B > 0 && (batch->x0 == nullptr) == (batch->x0_f32 == nullptr))
+    return fail(LINKS_ERR_ARG, "exactly one of x0 and x0_f32 must be given");
   if (opts->write == LINKS_WRITE_ALL && B > 0 && !out->path) return fail(LINKS_ERR_ARG, "path is NULL");
   if (opts->write == LINKS_WRITE_VALID &&
       (out->cap < 0 || !out->n_written || (out->cap > 0 && (!out->path_index || !out->path))))
@@ -348,6 +350,16 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   }
 
   using namespace links;
+  // single-precision positions: widened to double once (exactly), then the same path
+  links_batch wide;
+  if (!batch->x0) {
+    double* x0w;
+    if ((rc = ensure_t(ctx, "x0_wide", (size_t)B * J * 2, &x0w))) return rc;
+    if (phase == kRun) HIP_CHECK(launch_widen(batch->x0_f32, x0w, (size_t)B * J * 2, st));
+    wide = *batch;
+    wide.x0 = x0w;
+    batch = &wide;
+  }
   CandMeta* meta;
   CandF32* cf;
   CandF64* cd;

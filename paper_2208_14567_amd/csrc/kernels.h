@@ -57,6 +57,7 @@ hipError_t launch_prep_count(const PrepArgs& a, hipStream_t st);
 hipError_t launch_prep_offsets(const PrepArgs& a, hipStream_t st);
 hipError_t launch_prep_fill(const PrepArgs& a, hipStream_t st);
 hipError_t launch_fill_u32(void* p, size_t n_u32, uint32_t v, hipStream_t st);
+hipError_t launch_widen(const float* in, double* out, size_t n, hipStream_t st);
 size_t compact_scratch_ints(int32_t B);
 hipError_t launch_compact(int32_t B, const uint8_t* status, int32_t* scratch, int32_t* index, int32_t cap,
                           int32_t* total, int32_t* row_of, hipStream_t st);

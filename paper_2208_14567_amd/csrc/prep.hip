@@ -540,6 +540,19 @@ hipError_t launch_prep_fill(const PrepArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+__global__ void widen_kernel(const float* in, double* out, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) out[i] = (double)in[i];
+}
+
+hipError_t launch_widen(const float* in, double* out, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const size_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(widen_kernel, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, st, in, out, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(void* p, size_t n_u32, uint32_t v, hipStream_t st) {
   if (n_u32 == 0) return hipSuccess;
   size_t blocks = (n_u32 + 255) / 256;

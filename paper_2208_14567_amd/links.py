@@ -31,7 +31,8 @@ i32 = ctypes.c_int32
 
 
 class Batch(ctypes.Structure):
-    _fields_ = [("B", i32), ("J", i32), ("n", P), ("adj", P), ("fixed", P), ("motor", P), ("x0", P)]
+    _fields_ = [("B", i32), ("J", i32), ("n", P), ("adj", P), ("fixed", P), ("motor", P), ("x0", P),
+                ("x0_f32", P)]
 
 
 class SimOpts(ctypes.Structure):
@@ -144,18 +145,21 @@ class DeviceBatch:
         return int(self.adj.shape[1]) if self.adj.dim() == 2 else 1
 
     def cstruct(self) -> Batch:
-        return Batch(self.B, self.J, _ptr(self.n), _ptr(self.adj), _ptr(self.fixed), _ptr(self.motor), _ptr(self.x0))
+        f32 = self.x0.dtype == torch.float32
+        return Batch(self.B, self.J, _ptr(self.n), _ptr(self.adj), _ptr(self.fixed), _ptr(self.motor),
+                     None if f32 else _ptr(self.x0), _ptr(self.x0) if f32 else None)
 
     def slice(self, lo: int, hi: int) -> "DeviceBatch":
         return DeviceBatch(self.n[lo:hi], self.adj[lo:hi], self.fixed[lo:hi], self.motor[lo:hi], self.x0[lo:hi])
 
 
-def to_device(batch, device="cuda", non_blocking=False) -> DeviceBatch:
-    """Copies a host batch (paper_2208_14567_amd.gen.Batch) to the device."""
+def to_device(batch, device="cuda", non_blocking=False, x0_dtype=np.float64) -> DeviceBatch:
+    """Copies a host batch (paper_2208_14567_amd.gen.Batch) to the device; x0 in
+    double (default) or single precision (np.float32)."""
     def t(a, dtype):
         return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).to(device, non_blocking=non_blocking)
     return DeviceBatch(t(batch.n, np.uint8), t(batch.adj.view(np.int32), np.int32), t(batch.fixed.view(np.int32), np.int32),
-                       t(batch.motor, np.uint8), t(batch.x0, np.float64))
+                       t(batch.motor, np.uint8), t(batch.x0, x0_dtype))
 
 
 class Context:

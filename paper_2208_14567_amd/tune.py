@@ -32,7 +32,7 @@ SPACE: Dict[str, List[int]] = {
     "refill64": [8, 32],
 }
 
-DEFAULTS: Dict[str, int] = {"waves32": 1, "refill_min": 48, "chunk": 128, "spread": 1, "refill64": 32}
+DEFAULTS: Dict[str, int] = {"waves32": 4, "refill_min": 32, "chunk": 128, "spread": 1, "refill64": 32}
 
 
 def cache_path() -> str:

@@ -299,3 +299,17 @@ def test_bad_arguments_raise(ctx, L):
         ctx.simulate(b, out_joint=99)
     with pytest.raises(L.LinksError):
         ctx.normalize_paths(torch.zeros((2, 5000, 2), device="cuda"), L.NORM_PCA)
+
+
+def test_single_precision_positions_give_identical_results(ctx, L):
+    """The generator's positions are 24-bit uniforms, exact in FP32, so x0 passed
+    as float must give exactly the results of the same numbers passed as double."""
+    _say("[x0 f32]")
+    b = gen.workload("dyad_6_20", 20000, seed=13)
+    assert np.array_equal(b.x0.astype(np.float32).astype(np.float64), b.x0)
+    for prec in (L.FP32_RECHECK, L.FP64):
+        r64 = _np(ctx.simulate(L.to_device(b), precision=prec, write=L.WRITE_ALL))
+        r32 = _np(ctx.simulate(L.to_device(b, x0_dtype=np.float32), precision=prec, write=L.WRITE_ALL))
+        for k in ("status", "fail_step", "esc_step"):
+            assert np.array_equal(r64[k], r32[k]), (prec, k)
+        assert np.array_equal(np.nan_to_num(r64["path"], nan=7.0), np.nan_to_num(r32["path"], nan=7.0))
