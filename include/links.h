@@ -137,6 +137,12 @@ typedef struct {
   int32_t out_joint;   /* joint whose path is written; -1 = last joint of the solve order */
   int32_t write;       /* LINKS_WRITE_NONE | LINKS_WRITE_ALL | LINKS_WRITE_VALID */
   int32_t path_dtype;  /* LINKS_F32 | LINKS_F64 */
+  int32_t T_prefilter; /* 0: off.  Otherwise the low-fidelity check of "Scale of
+                        * Infeasibilities": every candidate is first simulated at
+                        * T_prefilter positions (T must be a multiple of it); those
+                        * that fail keep that status, with fail_step converted to the
+                        * same angle on the T grid (t * T / T_prefilter) and
+                        * esc_step -1, and only the survivors are simulated at T */
 } links_sim_opts;
 
 /* Fills opts with the defaults above (T = 200, WRITE_NONE, F32). */
@@ -213,6 +219,47 @@ int links_normalize_paths(links_ctx* ctx, const float* paths, int32_t P, int32_t
  * simulate -> normalise pipeline needs no host synchronisation. */
 int links_normalize_paths_n(links_ctx* ctx, const float* paths, const int32_t* count, int32_t cap, int32_t T,
                             int32_t mode, float* out, float* xform, void* stream);
+
+/* On-device generation of B dyad-built candidates (Methodology, "1-DOF Operator"
+ * and "Generating Valid Topologies"; positions as in "Finding Valid Initial
+ * Positions"): joint 0 fixed pivot, joint 1 actuated tip (link 0-1), joint 2
+ * fixed, and each joint k = 3..n-1 linked to two earlier joints that are not both
+ * fixed (21 draws of a pair, then the arm 0-1 as a fallback); n ~ U{n_lo..n_hi};
+ * every coordinate uniform in [0,1) with 24 random bits.  paper_mode = 1 adds, with
+ * probability 1/4, a linkless fixed joint in place of a linked one and sets the
+ * arm to pivot (0.5, 0.5), tip (0.55, 0.5).  Candidate i of the call is candidate
+ * first + i of the seed's sequence (SplitMix64 streams, Steele, Lea and Flood
+ * 2014), identical to the host generator of the Python package for the same
+ * seed, so a long stream can be generated in independent chunks.
+ * Outputs are device arrays in the links_batch layout (x0 as double), written
+ * asynchronously on `stream`.  Errors: LINKS_ERR_ARG for B < 0, first < 0,
+ * J outside [3, 32], joint counts outside [3, J], or a NULL array. */
+int links_generate_dyads(links_ctx* ctx, uint64_t seed, int64_t first, int32_t B, int32_t J, int32_t n_lo,
+                         int32_t n_hi, int32_t paper_mode, uint8_t* n, uint32_t* adj, uint32_t* fixed,
+                         uint8_t* motor, double* x0, void* stream);
+
+/* Curation of coupler paths (Methodology, "Dataset Curation & Processing").  Row i
+ * of norm_paths ([cap][T][2], DIAMETER-normalised by links_normalize_paths) is the
+ * path of joint out_joint (-1: the last joint of the solve order) of candidate
+ * path_index[i] of batch (path_index NULL: candidate i); only the first
+ * min(*count, cap) rows are processed (count: a DEVICE int32, for instance the
+ * n_written of a WRITE_VALID simulation; NULL: all cap rows).  Outputs per row:
+ *   flags      uint8   LINKS_CURATE_ARC when the joint is linked to a fixed joint
+ *                      (its path is an arc about that joint); LINKS_CURATE_CIRCLE
+ *                      when the population variance of the distances of the
+ *                      points from (0.5, 0.5) is below circle_var (the paper uses
+ *                      5e-4), computed in double
+ *   radial_var float   that variance
+ *   keep       uint32  joints of the reduced mechanism: the path's joint, its
+ *                      solve-order parents recursively, and the pivot when the
+ *                      actuated tip is among them (0 for an unsolvable candidate)
+ * Errors: LINKS_ERR_ARG for NULL arrays, cap < 0, T < 1, a bad out_joint, or
+ * cap > B without path_index. */
+#define LINKS_CURATE_ARC 1
+#define LINKS_CURATE_CIRCLE 2
+int links_curate(links_ctx* ctx, const links_batch* batch, const int32_t* path_index, const int32_t* count,
+                 int32_t cap, int32_t out_joint, const float* norm_paths, int32_t T, double circle_var,
+                 uint8_t* flags, float* radial_var, uint32_t* keep, void* stream);
 
 /* Replayable launch sequence.  links_graph_create records the passes of one
  * links_simulate call with exactly these arguments into a HIP graph (captured on

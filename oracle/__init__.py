@@ -84,6 +84,8 @@ def lib():
         L.links_ref_simulate.restype = ctypes.c_int
         L.links_ref_normalize_paths.argtypes = [P, i32, i32, i32, P, P]
         L.links_ref_normalize_paths.restype = ctypes.c_int
+        L.links_ref_curate.argtypes = [i32, P, P, P, P, i32, P, i32, P, i32, ctypes.c_double, P, P, P]
+        L.links_ref_curate.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -127,6 +129,49 @@ def simulate(batch, T: int = 200, out_joint: int = -1, tau_drift: float = TAU_DR
     if rc != 0:
         raise ValueError("links_ref_simulate: bad argument")
     return {"status": st, "fail_step": fs, "path": pa, "pos_all": al, "margins": mg}
+
+
+def simulate_prefiltered(batch, T: int = 200, T_low: int = 50, nthreads: int = 1, margins: bool = False):
+    """The low-fidelity screen of "Scale of Infeasibilities": every candidate is
+    simulated at T_low equally spaced actuator positions; those that lock there
+    are rejected (their failure kept, at the same angle on the T grid), and only
+    the survivors are simulated at T positions.  Returns status, fail_step and,
+    with margins, the margins of the run that decided each candidate."""
+    if T % T_low != 0 or not 0 < T_low < T:
+        raise ValueError("T_low must divide T and be smaller")
+    low = simulate(batch, T=T_low, nthreads=nthreads, margins=margins)
+    keep = np.nonzero(low["status"] == VALID)[0]
+    st = low["status"].copy()
+    fs = np.where(low["fail_step"] >= 0, low["fail_step"].astype(np.int32) * (T // T_low), -1).astype(np.int16)
+    mg = low["margins"].copy() if margins else None
+    if keep.size:
+        hi = simulate(batch.take(keep), T=T, nthreads=nthreads, margins=margins)
+        st[keep] = hi["status"]
+        fs[keep] = hi["fail_step"]
+        if margins:
+            mg[keep] = np.minimum(mg[keep], hi["margins"])
+    return {"status": st, "fail_step": fs, "margins": mg}
+
+
+ARC, CIRCLE = 1, 2
+CIRCLE_VAR = 5e-4
+
+
+def curate(batch, norm_paths: np.ndarray, cand=None, out_joint: int = -1, circle_var: float = CIRCLE_VAR):
+    """Arc and circle flags, radial variances and reduced-mechanism joint masks of
+    DIAMETER-normalised paths [P,T,2]; path i belongs to candidate cand[i]."""
+    p = _c(norm_paths, np.float64)
+    P, T = p.shape[0], p.shape[1]
+    cd = None if cand is None else _c(cand, np.int32)
+    fl = np.empty(P, np.uint8)
+    rv = np.empty(P, np.float64)
+    kp = np.empty(P, np.uint32)
+    n, adj, fx, mo = _c(batch.n, np.uint8), _c(batch.adj, np.uint32), _c(batch.fixed, np.uint32), _c(batch.motor, np.uint8)
+    rc = lib().links_ref_curate(batch.J, _p(n), _p(adj), _p(fx), _p(mo), out_joint, _p(cd), P, _p(p), T,
+                                circle_var, _p(fl), _p(rv), _p(kp))
+    if rc != 0:
+        raise ValueError("links_ref_curate: bad argument")
+    return {"flags": fl, "radial_var": rv, "keep": kp}
 
 
 def in_band(margins: np.ndarray, eps_disc: float = EPS_DISC, eps_branch: float = EPS_BRANCH,

@@ -532,3 +532,56 @@ int links_ref_normalize_paths(const double* paths, int32_t P, int32_t T, int32_t
   }
   return 0;
 }
+
+/* Curation (Methodology, "Dataset Curation & Processing"): arcs are recognised
+ * from the mechanism (the path's joint is linked to a ground joint), circles from
+ * the normalised path (small variance of the distances from the centre of the
+ * unit box), and a mechanism is reduced to the joints the path's joint depends on
+ * through the solve order. */
+int links_ref_curate(int32_t J, const uint8_t* n, const uint32_t* adj, const uint32_t* fixed,
+                     const uint8_t* motor, int32_t out_joint, const int32_t* cand, int32_t P,
+                     const double* norm, int32_t T, double circle_var, uint8_t* flags, double* radial_var,
+                     uint32_t* keep) {
+  if (P < 0 || T < 1 || J < 1 || J > MAXJ) return -1;
+  if (P > 0 && (!n || !adj || !fixed || !motor || !norm || !flags || !radial_var || !keep)) return -1;
+  for (int32_t i = 0; i < P; i++) {
+    const int32_t c = cand ? cand[i] : i;
+    const uint32_t* a = adj + (size_t)c * J;
+    const int pivot = motor[2 * c], tip = motor[2 * c + 1];
+    int8_t order[MAXJ * 3];
+    int nd = 0, dp = 0;
+    flags[i] = 0;
+    keep[i] = 0u;
+    /* radial variance of the normalised path about (0.5, 0.5), two passes */
+    const double* q = norm + (size_t)i * T * 2;
+    double mean = 0.0;
+    for (int t = 0; t < T; t++) {
+      double dx = q[2 * t] - 0.5, dy = q[2 * t + 1] - 0.5;
+      mean += sqrt(dx * dx + dy * dy);
+    }
+    mean /= (double)T;
+    double var = 0.0;
+    for (int t = 0; t < T; t++) {
+      double dx = q[2 * t] - 0.5, dy = q[2 * t + 1] - 0.5;
+      double e = sqrt(dx * dx + dy * dy) - mean;
+      var += e * e;
+    }
+    var /= (double)T;
+    radial_var[i] = var;
+    if (!solve_order_one(n[c], a, fixed[c], tip, order, &nd, &dp)) continue;
+    int out = out_joint >= 0 ? out_joint : (nd > 0 ? order[3 * (nd - 1)] : tip);
+    uint32_t f = 0u;
+    if (a[out] & fixed[c]) f |= LREF_CUR_ARC;
+    if (var < circle_var) f |= LREF_CUR_CIRCLE;
+    flags[i] = (uint8_t)f;
+    /* ancestors of the path's joint, walking the solve order backwards */
+    uint32_t m = 1u << out;
+    for (int s = nd - 1; s >= 0; s--) {
+      int k = order[3 * s];
+      if ((m >> k) & 1u) m |= (1u << order[3 * s + 1]) | (1u << order[3 * s + 2]);
+    }
+    if ((m >> tip) & 1u) m |= 1u << pivot;
+    keep[i] = m;
+  }
+  return 0;
+}

@@ -64,6 +64,25 @@ int links_ref_simulate(int32_t B, int32_t J, const uint8_t* n, const uint32_t* a
 int links_ref_normalize_paths(const double* paths, int32_t P, int32_t T, int32_t mode,
                               double* out, double* xform);
 
+/* Curation of coupler paths (Methodology, "Dataset Curation & Processing").
+ * Path i belongs to candidate cand[i] (cand NULL: candidate i); its joint is
+ * out_joint, or the last joint of the solve order when out_joint < 0.
+ *   flags[i]: bit 1 (ARC) when the joint is linked to a fixed joint (it turns
+ *     about that joint); bit 2 (CIRCLE) when the population variance of the
+ *     distances of the DIAMETER-normalised path norm[i] ([T][2]) from (0.5, 0.5)
+ *     is below circle_var.
+ *   radial_var[i]: that variance.
+ *   keep[i]: the joints needed to move the path joint: the joint, its solve-order
+ *     parents recursively, and the pivot when the tip is among them (the
+ *     reduced mechanism).
+ * Returns -1 on bad arguments (an unsolvable candidate gets keep = 0, flags 0). */
+#define LREF_CUR_ARC 1
+#define LREF_CUR_CIRCLE 2
+int links_ref_curate(int32_t J, const uint8_t* n, const uint32_t* adj, const uint32_t* fixed,
+                     const uint8_t* motor, int32_t out_joint, const int32_t* cand, int32_t P,
+                     const double* norm, int32_t T, double circle_var, uint8_t* flags, double* radial_var,
+                     uint32_t* keep);
+
 #ifdef __cplusplus
 }
 #endif

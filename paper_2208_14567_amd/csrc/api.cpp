@@ -219,6 +219,7 @@ void links_sim_opts_default(links_sim_opts* o) {
   o->out_joint = -1;
   o->write = LINKS_WRITE_NONE;
   o->path_dtype = LINKS_F32;
+  o->T_prefilter = 0;
 }
 
 int links_set_tuning(links_ctx* ctx, int waves32, int refill_min, int waves64) {
@@ -319,7 +320,7 @@ enum Phase { kPrepare = 0, kRun = 1 };
 
 // kPrepare: argument checks, workspace and crank table only; kRun: the whole call
 int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts* opts, links_sim_out* out,
-                  void* stream, int phase) {
+                  void* stream, int phase, int pre_ratio = 0) {
   if (!ctx) return fail(LINKS_ERR_ARG, "ctx is NULL");
   int rc = check_batch(batch);
   if (rc) return rc;
@@ -334,6 +335,26 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
     return fail(LINKS_ERR_ARG, "out_joint %d outside [-1, J)", opts->out_joint);
   if (!(opts->eps_disc >= 0) || !(opts->eps_branch >= 0) || !(opts->tau_drift >= 0))
     return fail(LINKS_ERR_ARG, "negative or NaN tolerance");
+  if (opts->T_prefilter != 0) {
+    const int Tp = opts->T_prefilter;
+    if (Tp < 1 || Tp >= T || T % Tp != 0)
+      return fail(LINKS_ERR_ARG, "T_prefilter = %d must divide T = %d and be smaller", Tp, T);
+    // low-fidelity pass: decisions only, into the caller's status arrays
+    links_sim_opts lo = *opts;
+    lo.T = Tp;
+    lo.T_prefilter = 0;
+    lo.write = LINKS_WRITE_NONE;
+    links_sim_out lo_out = *out;
+    lo_out.path = nullptr;
+    lo_out.path_index = nullptr;
+    lo_out.n_written = nullptr;
+    lo_out.cap = 0;
+    int r = simulate_impl(ctx, batch, &lo, &lo_out, stream, phase);
+    if (r) return r;
+    links_sim_opts hi = *opts;
+    hi.T_prefilter = 0;
+    return simulate_impl(ctx, batch, &hi, out, stream, phase, T / Tp);
+  }
   if (B > 0 && !out->status) return fail(LINKS_ERR_ARG, "status is NULL");
   if (B > 0 && (batch->x0 == nullptr) == (batch->x0_f32 == nullptr))
     return fail(LINKS_ERR_ARG, "exactly one of x0 and x0_f32 must be given");
@@ -413,6 +434,7 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   pa.x0 = batch->x0;
   pa.status = out->status;
   pa.sim = 1;
+  pa.pre_ratio = pre_ratio;
   pa.out_joint = opts->out_joint;
   pa.eps_disc = opts->eps_disc;
   pa.eps_branch = opts->eps_branch;
@@ -544,6 +566,68 @@ extern "C" {
 int links_simulate(links_ctx* ctx, const links_batch* batch, const links_sim_opts* opts, links_sim_out* out,
                    void* stream) {
   return simulate_impl(ctx, batch, opts, out, stream, kRun);
+}
+
+int links_generate_dyads(links_ctx* ctx, uint64_t seed, int64_t first, int32_t B, int32_t J, int32_t n_lo,
+                         int32_t n_hi, int32_t paper_mode, uint8_t* n, uint32_t* adj, uint32_t* fixed,
+                         uint8_t* motor, double* x0, void* stream) {
+  if (!ctx) return fail(LINKS_ERR_ARG, "ctx is NULL");
+  if (B < 0 || first < 0) return fail(LINKS_ERR_ARG, "B = %d or first = %lld is negative", B, (long long)first);
+  if (J < 3 || J > links::kMaxJ) return fail(LINKS_ERR_ARG, "J = %d outside [3, 32]", J);
+  if (n_lo < 3 || n_lo > n_hi || n_hi > J)
+    return fail(LINKS_ERR_ARG, "joint counts [%d, %d] not within [3, J = %d]", n_lo, n_hi, J);
+  if (paper_mode != 0 && paper_mode != 1) return fail(LINKS_ERR_ARG, "paper_mode must be 0 or 1");
+  if (B > 0 && (!n || !adj || !fixed || !motor || !x0)) return fail(LINKS_ERR_ARG, "NULL output array");
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  links::GenArgs g;
+  g.seed = seed;
+  g.first = first;
+  g.B = B;
+  g.J = J;
+  g.n_lo = n_lo;
+  g.n_hi = n_hi;
+  g.paper_mode = paper_mode;
+  g.n = n;
+  g.adj = adj;
+  g.fixed = fixed;
+  g.motor = motor;
+  g.x0 = x0;
+  HIP_CHECK(links::launch_gen_dyads(g, (hipStream_t)stream));
+  return LINKS_OK;
+}
+
+int links_curate(links_ctx* ctx, const links_batch* batch, const int32_t* path_index, const int32_t* count,
+                 int32_t cap, int32_t out_joint, const float* norm_paths, int32_t T, double circle_var,
+                 uint8_t* flags, float* radial_var, uint32_t* keep, void* stream) {
+  if (!ctx) return fail(LINKS_ERR_ARG, "ctx is NULL");
+  int rc = check_batch(batch);
+  if (rc) return rc;
+  if (cap < 0) return fail(LINKS_ERR_ARG, "cap = %d < 0", cap);
+  if (T < 1) return fail(LINKS_ERR_ARG, "T = %d < 1", T);
+  if (out_joint < -1 || out_joint >= batch->J) return fail(LINKS_ERR_ARG, "out_joint %d outside [-1, J)", out_joint);
+  if (!path_index && cap > batch->B) return fail(LINKS_ERR_ARG, "cap %d > B %d without path_index", cap, batch->B);
+  if (cap > 0 && (!norm_paths || !flags || !radial_var || !keep)) return fail(LINKS_ERR_ARG, "NULL array");
+  if (!(circle_var >= 0)) return fail(LINKS_ERR_ARG, "circle_var must be >= 0");
+  if ((rc = set_device(ctx))) return rc;
+  links::CurateArgs a;
+  a.J = batch->J;
+  a.T = T;
+  a.cap = cap;
+  a.out_joint = out_joint;
+  a.n = batch->n;
+  a.adj = batch->adj;
+  a.fixed = batch->fixed;
+  a.motor = batch->motor;
+  a.path_index = path_index;
+  a.count = count;
+  a.norm = norm_paths;
+  a.circle_var = circle_var;
+  a.flags = flags;
+  a.radial_var = radial_var;
+  a.keep = keep;
+  HIP_CHECK(links::launch_curate(a, (hipStream_t)stream));
+  return LINKS_OK;
 }
 
 int links_graph_create(links_ctx* ctx, const links_batch* batch, const links_sim_opts* opts, links_sim_out* out,

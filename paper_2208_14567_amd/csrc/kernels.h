@@ -31,6 +31,7 @@ struct PrepArgs {
   uint8_t* status;
   // simulation records (sim != 0)
   int32_t sim;
+  int32_t pre_ratio;  // > 0: candidates whose status is not VALID keep it (low-fidelity rejects)
   int32_t out_joint;
   double eps_disc, eps_branch, tau_drift;
   int16_t* fail_step;
@@ -58,6 +59,37 @@ hipError_t launch_prep_offsets(const PrepArgs& a, hipStream_t st);
 hipError_t launch_prep_fill(const PrepArgs& a, hipStream_t st);
 hipError_t launch_fill_u32(void* p, size_t n_u32, uint32_t v, hipStream_t st);
 hipError_t launch_widen(const float* in, double* out, size_t n, hipStream_t st);
+
+// on-device candidate generation (gen.hip)
+struct GenArgs {
+  uint64_t seed;
+  int64_t first;   // index of the first candidate in the seed's sequence
+  int64_t B;
+  int32_t J, n_lo, n_hi, paper_mode;
+  uint8_t* n;
+  uint32_t* adj;
+  uint32_t* fixed;
+  uint8_t* motor;
+  double* x0;
+};
+hipError_t launch_gen_dyads(const GenArgs& g, hipStream_t st);
+
+// curation of normalised coupler paths (prep.hip)
+struct CurateArgs {
+  int32_t J, T, cap, out_joint;
+  const uint8_t* n;
+  const uint32_t* adj;
+  const uint32_t* fixed;
+  const uint8_t* motor;
+  const int32_t* path_index;  // nullable: row i belongs to candidate i
+  const int32_t* count;       // nullable: cap rows
+  const float* norm;          // [cap][T][2] DIAMETER-normalised
+  double circle_var;
+  uint8_t* flags;
+  float* radial_var;
+  uint32_t* keep;
+};
+hipError_t launch_curate(const CurateArgs& a, hipStream_t st);
 size_t compact_scratch_ints(int32_t B);
 hipError_t launch_compact(int32_t B, const uint8_t* status, int32_t* scratch, int32_t* index, int32_t cap,
                           int32_t* total, int32_t* row_of, hipStream_t st);

@@ -189,7 +189,16 @@ __global__ void __launch_bounds__(kSortBlock) count_kernel(PrepArgs A) {
   const int tid = threadIdx.x;
   const int c = blockIdx.x * kSortBlock + tid;
   int dl = 0xFF;
-  if (c < A.B) {
+  bool rejected = false;
+  if (c < A.B && A.pre_ratio > 0 && A.status[c] != 0) {
+    // rejected by the low-fidelity pass: keep its decision, on the fine grid
+    rejected = true;
+    const int fs = A.fail_step[c];
+    if (fs >= 0) A.fail_step[c] = (int16_t)(fs * A.pre_ratio);
+    if (A.esc_step) A.esc_step[c] = -1;
+    A.dlen[c] = 0xFF;
+  }
+  if (c < A.B && !rejected) {
     const int J = A.J;
     const int n = A.n[c];
     const uint32_t fixed = A.fixed[c];
@@ -505,7 +514,76 @@ __global__ void __launch_bounds__(kScanBlock) write_sel_kernel(const int32_t* co
 }
 
 
+// Curation (Methodology, "Dataset Curation & Processing"), one wave per path: the
+// variance of the distances of the DIAMETER-normalised path from the centre of the
+// unit box (circles have none), whether the path's joint is linked to a ground
+// joint (it then turns on an arc about it), and the joints the path's joint depends
+// on through the solve order (the reduced mechanism).
+constexpr int kCurateBlock = 64;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__global__ void __launch_bounds__(kCurateBlock) curate_kernel(CurateArgs a) {
+  __shared__ uint32_t ord[kMaxJ];
+  __shared__ uint8_t idx[kMaxJ];
+  const int i = blockIdx.x;
+  const int rows = a.count ? min(*a.count, a.cap) : a.cap;
+  if (i >= rows) return;  // uniform over the workgroup
+  const int lane = threadIdx.x;
+  const int T = a.T;
+  const float2* q = reinterpret_cast<const float2*>(a.norm) + (size_t)i * T;
+  double s = 0.0;
+  for (int t = lane; t < T; t += kCurateBlock) {
+    const float2 p = q[t];
+    const double dx = (double)p.x - 0.5, dy = (double)p.y - 0.5;
+    s += sqrt(dx * dx + dy * dy);
+  }
+  const double mean = wave_sum(s) / (double)T;
+  double v = 0.0;
+  for (int t = lane; t < T; t += kCurateBlock) {
+    const float2 p = q[t];
+    const double dx = (double)p.x - 0.5, dy = (double)p.y - 0.5;
+    const double e = sqrt(dx * dx + dy * dy) - mean;
+    v += e * e;
+  }
+  const double var = wave_sum(v) / (double)T;
+  if (lane != 0) return;
+  const int c = a.path_index ? a.path_index[i] : i;
+  a.radial_var[i] = (float)var;
+  GlobalRow row;
+  row.adj = a.adj + (size_t)c * a.J;
+  row.x0 = nullptr;
+  const uint32_t fixed = a.fixed[c];
+  const int pivot = a.motor[2 * c], tip = a.motor[2 * c + 1];
+  int nd = 0, depth = 0;
+  uint32_t f = 0u, keep = 0u;
+  if (structure_ok(a.J, a.n[c], row, fixed, pivot, tip) &&
+      solve_rounds(a.n[c], row, fixed, tip, ord, idx, 1, &nd, &depth)) {
+    const int out = a.out_joint >= 0 ? a.out_joint : (nd > 0 ? (int)(ord[nd - 1] & 0xFF) : tip);
+    if (row.a(out) & fixed) f |= 1u;         // arc
+    if (var < a.circle_var) f |= 2u;         // circle
+    keep = 1u << out;
+    for (int k = nd - 1; k >= 0; k--) {
+      const uint32_t e = ord[k];
+      if ((keep >> (e & 0xFF)) & 1u) keep |= (1u << ((e >> 8) & 0xFF)) | (1u << ((e >> 16) & 0xFF));
+    }
+    if ((keep >> tip) & 1u) keep |= 1u << pivot;
+  }
+  a.flags[i] = (uint8_t)f;
+  a.keep[i] = keep;
+}
+
 }  // namespace
+
+hipError_t launch_curate(const CurateArgs& a, hipStream_t st) {
+  if (a.cap <= 0) return hipSuccess;
+  hipLaunchKernelGGL(curate_kernel, dim3(a.cap), dim3(kCurateBlock), 0, st, a);
+  return hipGetLastError();
+}
 
 hipError_t launch_solve_order(const PrepArgs& a, hipStream_t st) {
   if (a.B <= 0) return hipSuccess;

@@ -25,6 +25,7 @@ WRITE_NONE, WRITE_ALL, WRITE_VALID = 0, 1, 2
 F32, F64 = 0, 1
 NORM_PCA, NORM_DIAMETER = 0, 1
 NF_CONSTANT, NF_ISOTROPIC, NF_SIGN_TIE, NF_DIAM_TIE = 1, 2, 4, 8
+CURATE_ARC, CURATE_CIRCLE = 1, 2
 
 P = ctypes.c_void_p
 i32 = ctypes.c_int32
@@ -37,7 +38,8 @@ class Batch(ctypes.Structure):
 
 class SimOpts(ctypes.Structure):
     _fields_ = [("T", i32), ("precision", i32), ("eps_disc", ctypes.c_double), ("eps_branch", ctypes.c_double),
-                ("tau_drift", ctypes.c_double), ("out_joint", i32), ("write", i32), ("path_dtype", i32)]
+                ("tau_drift", ctypes.c_double), ("out_joint", i32), ("write", i32), ("path_dtype", i32),
+                ("T_prefilter", i32)]
 
 
 class SimOut(ctypes.Structure):
@@ -48,7 +50,8 @@ class SimOut(ctypes.Structure):
 EXPORTS = ["links_create", "links_destroy", "links_last_error", "links_version", "links_solve_order",
            "links_sim_opts_default", "links_simulate", "links_normalize_paths", "links_set_tuning",
            "links_get_tuning", "links_set_option", "links_normalize_paths_n", "links_profile", "links_last_timings",
-           "links_graph_create", "links_graph_launch", "links_graph_destroy", "links_get_option"]
+           "links_graph_create", "links_graph_launch", "links_graph_destroy", "links_get_option",
+           "links_generate_dyads", "links_curate"]
 TIMING_PASSES = ["prep_count", "prep_fill", "fp32_pass", "fp64_pass", "compaction", "path_pass"]
 
 _lib = None
@@ -93,6 +96,10 @@ def load() -> ctypes.CDLL:
     L.links_profile.restype = ctypes.c_int
     L.links_last_timings.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
     L.links_last_timings.restype = ctypes.c_int
+    L.links_generate_dyads.argtypes = [P, ctypes.c_uint64, ctypes.c_int64, i32, i32, i32, i32, i32, P, P, P, P, P, P]
+    L.links_generate_dyads.restype = ctypes.c_int
+    L.links_curate.argtypes = [P, ctypes.POINTER(Batch), P, P, i32, i32, P, i32, ctypes.c_double, P, P, P, P]
+    L.links_curate.restype = ctypes.c_int
     L.links_graph_create.argtypes = [P, ctypes.POINTER(Batch), ctypes.POINTER(SimOpts), ctypes.POINTER(SimOut),
                                      ctypes.POINTER(P)]
     L.links_graph_create.restype = ctypes.c_int
@@ -225,7 +232,7 @@ class Context:
 
     # ------------------------------------------------------------------ simulation
     def _sim_args(self, b: DeviceBatch, T, precision, write, out_joint, path_dtype, cap, eps_disc, eps_branch,
-                  tau_drift, out):
+                  tau_drift, out, T_prefilter=0):
         dev = b.n.device
         B = b.B
         o = out or {}
@@ -242,7 +249,7 @@ class Context:
             path = o.get("path") if o.get("path") is not None else torch.empty((max(cap_v, 1), T, 2), dtype=pdt, device=dev)
             idx = o.get("path_index") if o.get("path_index") is not None else torch.empty(max(cap_v, 1), dtype=torch.int32, device=dev)
             nw = o.get("n_written") if o.get("n_written") is not None else torch.empty(1, dtype=torch.int32, device=dev)
-        opts = SimOpts(T, precision, eps_disc, eps_branch, tau_drift, out_joint, write, path_dtype)
+        opts = SimOpts(T, precision, eps_disc, eps_branch, tau_drift, out_joint, write, path_dtype, T_prefilter)
         so = SimOut(_ptr(status), _ptr(fail), _ptr(esc), _ptr(path), _ptr(idx), _ptr(nw), cap_v)
         res = {"status": status, "fail_step": fail, "esc_step": esc}
         if path is not None:
@@ -254,14 +261,49 @@ class Context:
 
     def simulate(self, b: DeviceBatch, T: int = 200, precision: int = FP32_RECHECK, write: int = WRITE_NONE,
                  out_joint: int = -1, path_dtype: int = F32, cap: Optional[int] = None, eps_disc: float = 1e-6,
-                 eps_branch: float = 1e-5, tau_drift: float = 1e-4, out: Optional[dict] = None, stream=None):
+                 eps_branch: float = 1e-5, tau_drift: float = 1e-4, out: Optional[dict] = None, stream=None,
+                 T_prefilter: int = 0):
         """Returns a dict of device tensors: status, fail_step, esc_step and, by write
-        mode, path ([B,T,2] or [cap,T,2]), path_index and n_written."""
+        mode, path ([B,T,2] or [cap,T,2]), path_index and n_written.  T_prefilter > 0
+        runs the low-fidelity check at that many positions first."""
         cb, opts, so, res = self._sim_args(b, T, precision, write, out_joint, path_dtype, cap, eps_disc, eps_branch,
-                                           tau_drift, out)
+                                           tau_drift, out, T_prefilter)
         _check(load().links_simulate(self._h, ctypes.byref(cb), ctypes.byref(opts), ctypes.byref(so), _stream(stream)),
                "links_simulate")
         return res
+
+    def generate_dyads(self, B: int, seed: int, first: int = 0, J: int = 20, n_lo: int = 6, n_hi: int = 20,
+                       paper_mode: bool = False, device=None, out: Optional[DeviceBatch] = None,
+                       stream=None) -> DeviceBatch:
+        """Generates candidates first .. first+B-1 of the seed's sequence on the
+        device (the same candidates as gen.dyad_batch with n ~ U{n_lo..n_hi})."""
+        dev = torch.device("cuda", self.device) if device is None else device
+        if out is None:
+            out = DeviceBatch(torch.empty(B, dtype=torch.uint8, device=dev),
+                              torch.empty((B, J), dtype=torch.int32, device=dev),
+                              torch.empty(B, dtype=torch.int32, device=dev),
+                              torch.empty((B, 2), dtype=torch.uint8, device=dev),
+                              torch.empty((B, J, 2), dtype=torch.float64, device=dev))
+        _check(load().links_generate_dyads(self._h, seed & 0xFFFFFFFFFFFFFFFF, first, B, J, n_lo, n_hi,
+                                           1 if paper_mode else 0, _ptr(out.n), _ptr(out.adj), _ptr(out.fixed),
+                                           _ptr(out.motor), _ptr(out.x0), _stream(stream)), "links_generate_dyads")
+        return out
+
+    def curate(self, b: DeviceBatch, norm_paths: torch.Tensor, path_index: Optional[torch.Tensor] = None,
+               count: Optional[torch.Tensor] = None, out_joint: int = -1, circle_var: float = 5e-4,
+               stream=None) -> dict:
+        """Arc / circle flags, radial variances and reduced-mechanism joint masks of
+        DIAMETER-normalised paths (links_curate)."""
+        cap, T = int(norm_paths.shape[0]), int(norm_paths.shape[1])
+        dev = norm_paths.device
+        flags = torch.empty(max(cap, 1), dtype=torch.uint8, device=dev)
+        rv = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+        keep = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        cb = b.cstruct()
+        _check(load().links_curate(self._h, ctypes.byref(cb), _ptr(path_index), _ptr(count), cap, out_joint,
+                                   _ptr(norm_paths), T, circle_var, _ptr(flags), _ptr(rv), _ptr(keep),
+                                   _stream(stream)), "links_curate")
+        return {"flags": flags[:cap], "radial_var": rv[:cap], "keep": keep[:cap]}
 
     def graph(self, b: DeviceBatch, T: int = 200, precision: int = FP32_RECHECK, write: int = WRITE_NONE,
               out_joint: int = -1, path_dtype: int = F32, cap: Optional[int] = None, eps_disc: float = 1e-6,

@@ -313,3 +313,68 @@ def test_single_precision_positions_give_identical_results(ctx, L):
         for k in ("status", "fail_step", "esc_step"):
             assert np.array_equal(r64[k], r32[k]), (prec, k)
         assert np.array_equal(np.nan_to_num(r64["path"], nan=7.0), np.nan_to_num(r32["path"], nan=7.0))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_low_fidelity_prefilter(ctx, L, precision):
+    """T_prefilter = 50 (the paper's low-fidelity screen) against the oracle's
+    composition of a 50-position and a 200-position run: bit-exact for FP64, and
+    outside the bands for FP32 with escalation; valid paths are the full run's."""
+    _say(f"[prefilter] precision={precision}")
+    b = gen.workload("dyad_6_20", 20000, seed=14)
+    r = _np(ctx.simulate(L.to_device(b), T=200, precision=precision, T_prefilter=50, write=L.WRITE_VALID,
+                         cap=20000))
+    ref = oracle.simulate_prefiltered(b, T=200, T_low=50, margins=True, nthreads=NTH)
+    if precision == L.FP64:
+        assert np.array_equal(r["status"], ref["status"]) and np.array_equal(r["fail_step"], ref["fail_step"])
+    else:
+        clear = ~oracle.in_band(ref["margins"])
+        assert np.array_equal(r["status"][clear], ref["status"][clear])
+        assert np.array_equal(r["fail_step"][clear], ref["fail_step"][clear])
+    k = int(r["n_written"][0])
+    assert k == int((r["status"] == 0).sum())
+    full = oracle.simulate(b.take(r["path_index"][:k]), T=200, path=True, nthreads=NTH)
+    tol = 1e-5 * mech.scale_of(b.take(r["path_index"][:k]))
+    ok = full["status"] == 0          # in-band candidates may differ; they are excluded above
+    assert ok.mean() > 0.99
+    err = np.abs(r["path"][:k][ok] - full["path"][ok]).max(axis=(1, 2))
+    assert np.all(err <= tol[ok])
+
+
+def test_prefilter_argument_checks(ctx, L):
+    db = L.to_device(gen.workload("dyad_6_20", 100, seed=15))
+    for tp in (200, 33, -1):
+        with pytest.raises(L.LinksError):
+            ctx.simulate(db, T=200, T_prefilter=tp)
+
+
+def test_curation_parity(ctx, L):
+    """links_curate against the oracle's curation of the same DIAMETER-normalised
+    paths: arc flags and reduced-mechanism masks bit-exact, radial variances to
+    float rounding, circle flags exact away from the threshold."""
+    _say("[curate]")
+    b = gen.Batch.concat([gen.workload("dyad_6_20", 20000, seed=16), gen.workload("fourbar", 2000, seed=17)])
+    db = L.to_device(b)
+    r = ctx.simulate(db, write=L.WRITE_VALID, cap=b.B)
+    k = int(r["n_written"].cpu()[0])
+    norm, _ = ctx.normalize_paths(r["path"][:k].contiguous(), L.NORM_DIAMETER)
+    cu = ctx.curate(db, norm, path_index=r["path_index"][:k], count=r["n_written"])
+    got = {key: v.cpu().numpy() for key, v in cu.items()}
+    idx = r["path_index"][:k].cpu().numpy()
+    ref = oracle.curate(b, norm.cpu().numpy().astype(np.float64), cand=idx)
+    assert k > 2000
+    assert np.array_equal(got["keep"].view(np.uint32), ref["keep"])
+    assert np.array_equal(got["flags"] & 1, ref["flags"] & 1)
+    far = np.abs(ref["radial_var"] - oracle.CIRCLE_VAR) > 1e-9
+    assert np.array_equal(got["flags"][far] & 2, ref["flags"][far] & 2)
+    assert np.allclose(got["radial_var"], ref["radial_var"], rtol=1e-6, atol=1e-12)
+    arcs, circles = (ref["flags"] & 1).mean(), ((ref["flags"] & 2) != 0).mean()
+    _say(f"   {k} paths: arcs {arcs:.3f}, circles {circles:.3f}")
+    # the crank tip of a four-bar: an arc and a circle
+    fb = gen.workload("fourbar", 500, seed=18)
+    dfb = L.to_device(fb)
+    rr = ctx.simulate(dfb, out_joint=1, write=L.WRITE_ALL)
+    nf, _ = ctx.normalize_paths(rr["path"], L.NORM_DIAMETER)
+    cf = ctx.curate(dfb, nf, out_joint=1)
+    assert np.all(cf["flags"].cpu().numpy() == 3)
+    assert np.all(cf["keep"].cpu().numpy() == 3)

@@ -191,3 +191,29 @@ def test_discriminant_and_distance_margins_closed_form(oracle_lib):
         assert abs(m[0] - want_disc) <= 1e-9 * max(want_disc, 1e-12), (c, m[0], want_disc)
         assert abs(m[1] - want_deg) <= 1e-9 * want_deg, (c, m[1], want_deg)
         assert np.isinf(m[3])   # no redundant link, no drift check
+
+
+def test_low_fidelity_screen_on_the_coarse_grid(oracle_lib):
+    """The 50-position screen is the 200-position rule evaluated on every fourth
+    angle: for four-bars, whose only lockable joint is decided by the law of
+    cosines at each angle independently of the branch history, a candidate
+    rejected on the coarse grid fails at the first coarse angle where the fine
+    grid also fails (same status), and every survivor gets the full 200-step
+    decision."""
+    T = 200
+    b = gen.workload("fourbar_u", 3000, seed=61)
+    full = oracle.simulate(b, T=T)
+    pre = oracle.simulate_prefiltered(b, T=T, T_low=50)
+    st50, fs50, m50 = _lock_prediction(b, 50)
+    clear = m50 > 1e-9
+    rej = pre["status"] != oracle.VALID
+    # rejected on the coarse grid: the law-of-cosines prediction at T = 50, mapped to the fine grid
+    coarse_bad = clear & (st50 != oracle.VALID)
+    assert np.array_equal(rej[clear] & coarse_bad[clear], coarse_bad[clear])
+    assert np.array_equal(pre["fail_step"][coarse_bad], fs50[coarse_bad].astype(np.int16) * 4)
+    # survivors of the screen carry the full simulation's decision
+    surv = pre["status"] == oracle.VALID
+    assert np.all(full["status"][surv] == oracle.VALID)
+    keep = ~coarse_bad & clear
+    assert np.array_equal(pre["status"][keep], full["status"][keep])
+    assert np.array_equal(pre["fail_step"][keep], full["fail_step"][keep])

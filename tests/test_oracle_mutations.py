@@ -10,6 +10,7 @@ import pytest
 import oracle
 from tests import test_oracle_fixtures as fx
 from tests import test_oracle_fourbar as fb
+from tests import test_oracle_curate as cu
 from tests import test_oracle_order as od
 
 MUTATIONS = {
@@ -31,6 +32,10 @@ MUTATIONS = {
                          "for (int k = n - 1; k >= 0; k--) {\n      if ((known >> k) & 1u) continue;"),
     "drift_ignored": ("if (drift > A->tau_drift * scale) {", "if (drift > 1e9 * A->tau_drift * scale) {"),
     "skip_last_step": ("for (int t = 0; t < T; t++) {\n    /* actuator", "for (int t = 0; t < T - 1; t++) {\n    /* actuator"),
+    "radial_not_squared": ("      var += e * e;", "      var += fabs(e);"),
+    "ancestors_forward": ("for (int s = nd - 1; s >= 0; s--) {\n      int k = order[3 * s];",
+                          "for (int s = 0; s < nd; s++) {\n      int k = order[3 * s];"),
+    "arc_any_link": ("if (a[out] & fixed[c]) f |= LREF_CUR_ARC;", "if (a[out]) f |= LREF_CUR_ARC;"),
 }
 
 PINS = [
@@ -41,6 +46,9 @@ PINS = [
     lambda: od.test_order_matches_brute_force_on_small_random_graphs(None),
     lambda: fx.test_redundant_links_drift(None),
     lambda: fx.test_locking_step(None),
+    lambda: cu.test_fourbar_arcs_circles_and_reduction(None),
+    lambda: cu.test_radial_variance_of_an_ellipse(None),
+    lambda: cu.test_reduced_mechanism_reproduces_the_path(None),
 ]
 
 
