@@ -393,6 +393,7 @@ def main():
                     help="arithmetic of the FP64 hand-over pass")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch parameters")
+    ap.add_argument("--no-pipeline", action="store_true", help="skip the two-stream pipelined leg")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--chunks", type=int, default=25, help="cfg5: chunks of 4M candidates")
     ap.add_argument("--config", choices=["cfg2", "cfg1", "cfg1x", "cfg3", "cfg5"], default="cfg2",
@@ -529,6 +530,34 @@ def main():
         cpu["one_core"] = {"value": one.B / w1, "sample": f"first {one.B} candidates, 1 thread, {w1:.2f} s"}
         log(f"cpu oracle, one core: {one.B / w1:.0f} sims/s")
 
+    # the same steps issued alternately on two contexts and streams, so one step's
+    # low-occupancy phases (hand-over and path-pass tails) overlap the next step
+    pipelined = None
+    if not args.no_pipeline:
+        lanes = []
+        for _ in range(2):
+            c = L.Context(0)
+            if tuned:
+                tune.apply(c, tuned["config"])
+            o = {k: torch.empty_like(v) for k, v in out.items()}
+            lanes.append((c, torch.cuda.Stream(device=dev), o, torch.empty_like(norm_out), torch.empty_like(norm_xf)))
+
+        def pstep(i):
+            c, st_, o, no, nx = lanes[i % 2]
+            c.simulate(db, T=T, precision=L.FP32_RECHECK, write=L.WRITE_VALID, cap=B, out=o, stream=st_)
+            c.normalize_paths_n(o["path"], o["n_written"], L.NORM_PCA, out=no, xform=nx, stream=st_)
+
+        for i in range(2 * args.warmup):
+            pstep(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            pstep(i)
+        torch.cuda.synchronize()
+        dtp = (time.perf_counter() - t0) / args.steps
+        pipelined = {"value": B / dtp, "ms_per_step": dtp * 1e3, "streams": 2}
+        log(f"pipelined on two streams: {dtp * 1e3:.3f} ms/step")
+
     serving = None
     if not args.no_serve:
         serving = serve_leg(L, gen, dev, args.serve_requests, tuned["config"] if tuned else None)
@@ -560,6 +589,7 @@ def main():
                      "dyad_steps": int(dsteps32.sum()), "candidate_steps": int(steps32.sum())},
         "cpu_baseline": cpu,
         "fp64_plain": fp64,
+        "pipelined": pipelined,
         "serving": serving,
         "end_to_end": e2e,
         "stats": stats,

@@ -185,6 +185,10 @@ int links_simulate(links_ctx* ctx, const links_batch* batch, const links_sim_opt
 int links_set_tuning(links_ctx* ctx, int waves32, int refill_min, int waves64);
 /* Named integer options (LINKS_ERR_ARG for an unknown name or value):
  *   "waves32", "refill_min", "waves64"  as in links_set_tuning;
+ *   "deesc"           FP32_RECHECK: a candidate handed over to FP64 returns to FP32
+ *                     after this many FP64 steps (positions rounded to FP32, error
+ *                     bounds restarted as at t = 0); what it hands over again is
+ *                     finished in FP64.  0 (default) keeps it in FP64 to the end;
  *   "chunk"           list items a wave claims with one atomic operation and
  *                     then hands to its lanes as they free up (1..4096, default 128);
  *   "spread"          1 (default): waves of the FP32 pass start spread over the

@@ -53,6 +53,7 @@ struct links_ctx {
   int refill64 = 32;           // refill threshold of the FP64 passes
   int spread = 1;              // FP32 waves start spread over the solve-order buckets
   int chunk = 128;             // list items a wave claims per atomic
+  int deesc = 0;               // FP64 steps after a hand-over before returning to FP32 (0: never)
   bool exact_handover = false;  // FP64 hand-over pass with the correctly rounded sequence (else rsq + Newton)
   std::map<std::string, int> occ_cache;
   // last call's statistics
@@ -238,6 +239,11 @@ int links_set_option(links_ctx* ctx, const char* name, int value) {
   if (k == "waves32") return links_set_tuning(ctx, value, ctx->refill_min, ctx->waves64);
   if (k == "refill_min") return links_set_tuning(ctx, ctx->waves32, value, ctx->waves64);
   if (k == "waves64") return links_set_tuning(ctx, ctx->waves32, ctx->refill_min, value);
+  if (k == "deesc") {
+    if (value < 0 || value > 32767) return fail(LINKS_ERR_ARG, "deesc must be in 0..32767");
+    ctx->deesc = value;
+    return LINKS_OK;
+  }
   if (k == "chunk") {
     if (value < 1 || value > 4096) return fail(LINKS_ERR_ARG, "chunk must be in 1..4096");
     ctx->chunk = value;
@@ -270,6 +276,7 @@ int links_get_option(links_ctx* ctx, const char* name, int* value) {
   else if (k == "refill64") *value = ctx->refill64;
   else if (k == "chunk") *value = ctx->chunk;
   else if (k == "spread") *value = ctx->spread;
+  else if (k == "deesc") *value = ctx->deesc;
   else if (k == "exact_handover") *value = ctx->exact_handover ? 1 : 0;
   else return fail(LINKS_ERR_ARG, "unknown option '%s'", name);
   return LINKS_OK;
@@ -392,6 +399,11 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   int32_t* counters;
   EscEntry* esc;
   float2* esc_pos;
+  EscEntry* res;
+  float2* res_pos;
+  EscEntry* esc2;
+  float2* esc2_pos;
+  int32_t* counters2;
   int16_t* fail_ws;
   int32_t* path_list;
   int32_t* path_row;
@@ -406,6 +418,9 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
       (rc = ensure_t(ctx, "sj", (size_t)B * J, &sj)) || (rc = ensure_t(ctx, "perm", B, &perm)) ||
       (rc = ensure_t(ctx, "counters", kCntSize, &counters)) || (rc = ensure_t(ctx, "esc", B, &esc)) ||
       (rc = ensure_t(ctx, "esc_pos", (size_t)B * J, &esc_pos)) || (rc = ensure_t(ctx, "fail_ws", B, &fail_ws)) ||
+      (rc = ensure_t(ctx, "res", B, &res)) || (rc = ensure_t(ctx, "res_pos", (size_t)B * J, &res_pos)) ||
+      (rc = ensure_t(ctx, "esc2", B, &esc2)) || (rc = ensure_t(ctx, "esc2_pos", (size_t)B * J, &esc2_pos)) ||
+      (rc = ensure_t(ctx, "counters2", kCntSize, &counters2)) ||
       (rc = ensure_t(ctx, "path_list", B, &path_list)) || (rc = ensure_t(ctx, "path_row", B, &path_row)) ||
       (rc = ensure_t(ctx, "dlen", B, &dlen)) ||
       (rc = ensure_t(ctx, "block_hist", nblocks * kMaxJ, &block_hist)) ||
@@ -502,6 +517,10 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   sa.nslot = J;
   sa.refill_min = ctx->refill_min;
   sa.spread = ctx->spread;
+  sa.res = res;
+  sa.res_pos = res_pos;
+  sa.deesc = 0;
+  sa.resume = 0;
   sa.chunk = ctx->chunk;
 
   LaunchCfg c64;
@@ -529,7 +548,26 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
     ctx->ev_used[2] = true;
     c64.grid = grid_for(ctx, "sim64", sim64_blocks_per_cu(J, kFromEsc, ctx->exact_handover, c64.waves, lds64));
     if ((rc = mark(ctx, 3, st))) return rc;
-    HIP_CHECK(launch_sim64(sa64, kFromEsc, ctx->exact_handover, c64, st));
+    SimArgs h1 = sa64;
+    h1.deesc = ctx->deesc;
+    HIP_CHECK(launch_sim64(h1, kFromEsc, ctx->exact_handover, c64, st));
+    if (ctx->deesc > 0) {
+      // the returned candidates continue in FP32 (their own counters and
+      // hand-over queue), and what they hand over again is finished in FP64
+      HIP_CHECK(launch_resume_setup(counters, counters2, st));
+      SimArgs r32 = sa;
+      r32.counters = counters2;
+      r32.resume = 1;
+      r32.esc = esc2;
+      r32.esc_pos = esc2_pos;
+      HIP_CHECK(launch_sim32(r32, mode, c32, st));
+      SimArgs h2 = sa64;
+      h2.counters = counters2;
+      h2.esc = esc2;
+      h2.esc_pos = esc2_pos;
+      h2.deesc = 0;
+      HIP_CHECK(launch_sim64(h2, kFromEsc, ctx->exact_handover, c64, st));
+    }
     ctx->ev_used[3] = true;
     ctx->last_grid32 = c32.grid;
   }

@@ -112,6 +112,13 @@ struct SimArgs {
   int32_t refill_min;  // refill a wave when at least this many lanes are idle
   int32_t spread;      // FP32 pass: waves start spread over the buckets (1) or all in the largest (0)
   int32_t chunk;       // items a wave claims with one atomic
+  // returning to FP32 after a hand-over: the FP64 pass stops a candidate deesc
+  // steps after its hand-over step and queues it (res, res_pos); a resume round of
+  // the FP32 pass (resume = 1) takes its work items from that queue
+  EscEntry* res;       // [B] (sorted position, next step)
+  float2* res_pos;     // [B][J] slot positions at the end of the last FP64 step
+  int32_t deesc;       // 0: the FP64 pass finishes every candidate it takes
+  int32_t resume;
 };
 
 }  // namespace links

@@ -15,7 +15,8 @@ constexpr int kCntPathNext = 6;
 constexpr int kCntHist = 8;     // [32] histogram of solve-order lengths
 constexpr int kCntOff = 40;     // [32] bucket offsets
 constexpr int kCntCur = 72;     // [32] next item of each bucket (FP32 pass)
-constexpr int kCntSize = 104;
+constexpr int kCntRes = 104;    // candidates returned from the FP64 hand-over to FP32
+constexpr int kCntSize = 112;
 
 struct PrepArgs {
   int32_t B, J;
@@ -59,6 +60,8 @@ hipError_t launch_prep_offsets(const PrepArgs& a, hipStream_t st);
 hipError_t launch_prep_fill(const PrepArgs& a, hipStream_t st);
 hipError_t launch_fill_u32(void* p, size_t n_u32, uint32_t v, hipStream_t st);
 hipError_t launch_widen(const float* in, double* out, size_t n, hipStream_t st);
+// counters of a resume round: every returned candidate in one bucket (prep.hip)
+hipError_t launch_resume_setup(const int32_t* counters, int32_t* counters2, hipStream_t st);
 
 // on-device candidate generation (gen.hip)
 struct GenArgs {

@@ -618,6 +618,22 @@ hipError_t launch_prep_fill(const PrepArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+__global__ void resume_setup_kernel(const int32_t* counters, int32_t* counters2) {
+  const int i = threadIdx.x;
+  if (i < kCntSize) counters2[i] = 0;
+  __syncthreads();
+  if (i == 0) {
+    const int r = counters[kCntRes];
+    counters2[kCntHist + 0] = r;
+    counters2[kCntItems] = r;
+  }
+}
+
+hipError_t launch_resume_setup(const int32_t* counters, int32_t* counters2, hipStream_t st) {
+  hipLaunchKernelGGL(resume_setup_kernel, dim3(1), dim3(128), 0, st, counters, counters2);
+  return hipGetLastError();
+}
+
 __global__ void widen_kernel(const float* in, double* out, size_t n) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t stride = (size_t)gridDim.x * blockDim.x;

@@ -191,10 +191,22 @@ sim32_kernel(SimArgs A) {
       }
       if (cand < 0 && p >= 0) {
         {
+          // a resume round's work item is an entry of the queue of candidates the
+          // FP64 pass returned: its sorted position, next step and positions
+          int t0 = 0;
+          const float2* init = A.x0s + p;
+          size_t init_stride = (size_t)Bs;
+          if (A.resume) {
+            const EscEntry e = A.res[p];
+            init = A.res_pos + (size_t)p * J;
+            init_stride = 1;
+            t0 = e.t;
+            p = e.item;
+          }
           const int c = A.perm[p];
           cand = c;
           item = p;
-          t = 0;
+          t = t0;
           CandMeta m = A.meta[p];
           D = m.D;
           n = m.n;
@@ -234,7 +246,7 @@ sim32_kernel(SimArgs A) {
             float2 xq[G];
 #pragma unroll
             for (int k = 0; k < G; ++k)
-              if (g + k < n) xq[k] = A.x0s[(size_t)(g + k) * Bs + p];
+              if (g + k < n) xq[k] = init[(size_t)(g + k) * init_stride];
 #pragma unroll
             for (int k = 0; k < G; ++k)
               if (g + k < n) {
@@ -346,7 +358,7 @@ sim32_kernel(SimArgs A) {
       if (lock_ev) {
         A.status[cand] = (uint8_t)lock_kind;
         A.fail_step[cand] = (int16_t)t;
-        if (A.esc_step) A.esc_step[cand] = -1;
+        if (A.esc_step && !A.resume) A.esc_step[cand] = -1;
       } else {
         int i = atomicAdd(&A.counters[kCntEsc], 1);
         EscEntry e;
@@ -357,13 +369,13 @@ sim32_kernel(SimArgs A) {
         A.esc[i] = e;
         float2* dump = A.esc_pos + (size_t)i * J;
         for (int sl = 0; sl < n; ++sl) dump[sl] = P[sl * bd + tid];
-        if (A.esc_step) A.esc_step[cand] = (int16_t)t;
+        if (A.esc_step && !A.resume) A.esc_step[cand] = (int16_t)t;  // the first hand-over
       }
       done = true;
     } else if (++t == T) {
       A.status[cand] = 0;
       A.fail_step[cand] = -1;
-      if (A.esc_step) A.esc_step[cand] = -1;
+      if (A.esc_step && !A.resume) A.esc_step[cand] = -1;
       done = true;
     }
     if (done) cand = -1;

@@ -101,6 +101,7 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
   const int cnt_items = SRC == kFromEsc ? kCntEsc : SRC == kFromPath ? kCntPath : kCntItems;
 
   int cand = -1, item = 0, t = 0, t_end = 0, D = 0, n = 0, out_slot = 0;
+  int t_back = 0x7FFF;  // hand-over pass: step from which the candidate returns to FP32
   int64_t row = -1;  // path row (kFromPath)
   bool redundant = false;
   double px = 0, py = 0, vx = 0, vy = 0, deg_thr = 0, drift_thr = 0;
@@ -180,6 +181,7 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
           const int c = A.perm[it];
           item = it;
           t = t0;
+          t_back = 0x7FFF;
           t_end = T;
           bool take = true;
           if (SRC == kFromPath) {
@@ -195,6 +197,8 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
             n = m.n;
             out_slot = m.out_slot;
             redundant = (m.flags & kFlagRedundant) != 0;
+            // drift checks need FP64 lengths, so those candidates stay
+            if (SRC == kFromEsc && A.deesc > 0 && !redundant) t_back = t + A.deesc;
             const CandF64 f = A.cd[it];
             px = f.px;
             py = f.py;
@@ -354,6 +358,21 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
         A.status[cand] = 0;
         A.fail_step[cand] = -1;
         if (SRC == kFromPerm && A.esc_step) A.esc_step[cand] = -1;
+        done = true;
+      } else if (SRC == kFromEsc && t >= t_back) {
+        // decided in FP64 up to here: back to FP32 from step t with these positions
+        const int r = atomicAdd(&A.counters[kCntRes], 1);
+        EscEntry e;
+        e.item = item;
+        e.t = (int16_t)t;
+        e.from_x0 = 0;
+        e.pad = 0;
+        A.res[r] = e;
+        float2* dump = A.res_pos + (size_t)r * J;
+        for (int sl = 0; sl < n; ++sl) {
+          const double2 q = P[sl * bd + tid];
+          dump[sl] = make_float2((float)q.x, (float)q.y);
+        }
         done = true;
       }
       if (done) cand = -1;

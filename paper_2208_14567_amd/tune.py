@@ -8,6 +8,7 @@ workload (batch size, joint-count mix, step count) and the device:
   chunk       list items a wave claims with one atomic (guided down near the end)
   spread      FP32 waves start spread over the solve-order buckets or all at the top
   refill64    refill threshold of the FP64 passes
+  deesc       FP64 steps after a hand-over before a candidate returns to FP32
 
 `autotune` runs the real pass sequence on the caller's batch, timing each
 candidate setting with the library's own HIP events, and searches coordinate by
@@ -30,9 +31,10 @@ SPACE: Dict[str, List[int]] = {
     "chunk": [32, 64, 128, 256],
     "spread": [1, 0],
     "refill64": [8, 32],
+    "deesc": [0, 8],
 }
 
-DEFAULTS: Dict[str, int] = {"waves32": 4, "refill_min": 32, "chunk": 128, "spread": 1, "refill64": 32}
+DEFAULTS: Dict[str, int] = {"waves32": 4, "refill_min": 32, "chunk": 128, "spread": 1, "refill64": 32, "deesc": 0}
 
 
 def cache_path() -> str:
@@ -76,7 +78,7 @@ def coordinate_search(measure: Callable[[Dict[str, int]], float], space: Dict[st
 def apply(ctx, cfg: Dict[str, int]):
     cur = ctx.get_tuning()
     ctx.set_tuning(cfg.get("waves32", cur["waves32"]), cfg.get("refill_min", cur["refill_min"]), cur["waves64"])
-    for k in ("chunk", "spread", "refill64"):
+    for k in ("chunk", "spread", "refill64", "deesc"):
         if k in cfg:
             ctx.set_option(k, cfg[k])
 

@@ -378,3 +378,16 @@ def test_curation_parity(ctx, L):
     cf = ctx.curate(dfb, nf, out_joint=1)
     assert np.all(cf["flags"].cpu().numpy() == 3)
     assert np.all(cf["keep"].cpu().numpy() == 3)
+
+
+@pytest.mark.parametrize("deesc", [1, 4, 8])
+def test_return_to_fp32_after_handover(ctx, L, deesc):
+    """The same bar whatever the number of FP64 steps before a handed-over
+    candidate returns to FP32 (0: never returns)."""
+    _say(f"[deesc] {deesc}")
+    b = gen.workload("dyad_6_20", 20000, seed=19)
+    ctx.set_option("deesc", deesc)
+    try:
+        _fp32_parity(ctx, L, b, label=f"deesc={deesc}")
+    finally:
+        ctx.set_option("deesc", 0)

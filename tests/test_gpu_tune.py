@@ -22,11 +22,12 @@ def test_autotune_applies_and_caches(tmp_path):
     db = L.to_device(gen.workload("dyad_6_20", 40000, seed=8))
     ref = {k: v.cpu().numpy() for k, v in ctx.simulate(db, write=L.WRITE_VALID, cap=40000).items()}
     space = {"waves32": [1, 4], "refill_min": [16, 48], "chunk": [64, 128]}
+    start = tune.current(ctx)
     path = str(tmp_path / "tune.json")
     r = tune.autotune(ctx, db, space=space, path=path)
     assert not r["cached"] and r["measurements"] >= 1 and os.path.exists(path)
     for k, v in r["config"].items():
-        assert v in space.get(k, [v])
+        assert v in space.get(k, []) + [start[k]]     # a searched value, or the start it kept
         assert ctx.get_option(k) == v
     got = {k: v.cpu().numpy() for k, v in ctx.simulate(db, write=L.WRITE_VALID, cap=40000).items()}
     for k in ("status", "fail_step", "esc_step", "n_written", "path_index"):
