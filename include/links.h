@@ -199,7 +199,13 @@ int links_set_tuning(links_ctx* ctx, int waves32, int refill_min, int waves64);
  *   "exact_handover"  0 (default): the FP64 hand-over pass uses reciprocal square
  *                     roots refined by Newton steps (relative error ~1e-15); 1: the
  *                     correctly rounded sequence of the FP64 precision (the
- *                     operations of an IEEE double evaluation, as in LINKS_FP64). */
+ *                     operations of an IEEE double evaluation, as in LINKS_FP64);
+ *   "par64"           which FP64 passes run parallel in time: 16 lanes share one
+ *                     candidate, each computing one step with every dyad on an
+ *                     assumed side, checked against the continuity rule and
+ *                     restarted where the rule changes side (results identical to
+ *                     the step-by-step pass).  0: none; 1 (default): the hand-over
+ *                     pass (whose long FP64 runs are few); 2: every FP64 pass. */
 int links_set_option(links_ctx* ctx, const char* name, int value);
 /* Current value of a named option in *value (LINKS_ERR_ARG for an unknown name). */
 int links_get_option(links_ctx* ctx, const char* name, int* value);

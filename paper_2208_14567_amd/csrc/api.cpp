@@ -16,6 +16,19 @@
 
 namespace {
 
+// The largest double t with sqrt(t) <= 1e-12: a link of squared length d2 is
+// longer than 1e-12 exactly when d2 > t (sqrt is monotone and correctly rounded).
+double len2_min() {
+  static const double t = [] {
+    double v = 1e-12 * 1e-12;
+    while (std::sqrt(v) > 1e-12) v = std::nextafter(v, 0.0);
+    while (std::sqrt(std::nextafter(v, 1.0)) <= 1e-12) v = std::nextafter(v, 1.0);
+    return v;
+  }();
+  return t;
+}
+
+
 thread_local std::string g_err;
 
 int fail(int code, const char* fmt, ...) {
@@ -55,6 +68,10 @@ struct links_ctx {
   int chunk = 128;             // list items a wave claims per atomic
   int deesc = 0;               // FP64 steps after a hand-over before returning to FP32 (0: never)
   bool exact_handover = false;  // FP64 hand-over pass with the correctly rounded sequence (else rsq + Newton)
+  // FP64 passes computed parallel in time (16-lane segments per candidate):
+  // 0 none, 1 the hand-over pass, 2 every FP64 pass.  The return to FP32 after a
+  // hand-over (deesc > 0) keeps the step-by-step pass.
+  int par64 = 1;
   std::map<std::string, int> occ_cache;
   // last call's statistics
   int last_grid32 = 0, last_grid64 = 0;
@@ -264,6 +281,11 @@ int links_set_option(links_ctx* ctx, const char* name, int value) {
     ctx->exact_handover = value != 0;
     return LINKS_OK;
   }
+  if (k == "par64") {
+    if (value < 0 || value > 2) return fail(LINKS_ERR_ARG, "par64 must be 0, 1 or 2");
+    ctx->par64 = value;
+    return LINKS_OK;
+  }
   return fail(LINKS_ERR_ARG, "unknown option '%s'", name);
 }
 
@@ -278,6 +300,7 @@ int links_get_option(links_ctx* ctx, const char* name, int* value) {
   else if (k == "spread") *value = ctx->spread;
   else if (k == "deesc") *value = ctx->deesc;
   else if (k == "exact_handover") *value = ctx->exact_handover ? 1 : 0;
+  else if (k == "par64") *value = ctx->par64;
   else return fail(LINKS_ERR_ARG, "unknown option '%s'", name);
   return LINKS_OK;
 }
@@ -408,6 +431,8 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   int32_t* path_list;
   int32_t* path_row;
   uint8_t* dlen;
+  double* scale_ws;
+  int16_t* movable_ws;
   int32_t* block_hist;
   int32_t* block_off;
   int32_t* scratch;
@@ -422,7 +447,8 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
       (rc = ensure_t(ctx, "esc2", B, &esc2)) || (rc = ensure_t(ctx, "esc2_pos", (size_t)B * J, &esc2_pos)) ||
       (rc = ensure_t(ctx, "counters2", kCntSize, &counters2)) ||
       (rc = ensure_t(ctx, "path_list", B, &path_list)) || (rc = ensure_t(ctx, "path_row", B, &path_row)) ||
-      (rc = ensure_t(ctx, "dlen", B, &dlen)) ||
+      (rc = ensure_t(ctx, "dlen", B, &dlen)) || (rc = ensure_t(ctx, "scale_ws", B, &scale_ws)) ||
+      (rc = ensure_t(ctx, "movable_ws", B, &movable_ws)) ||
       (rc = ensure_t(ctx, "block_hist", nblocks * kMaxJ, &block_hist)) ||
       (rc = ensure_t(ctx, "block_off", nblocks * kMaxJ, &block_off)) ||
       (rc = ensure_t(ctx, "compact", compact_scratch_ints(B), &scratch)))
@@ -454,6 +480,7 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   pa.eps_disc = opts->eps_disc;
   pa.eps_branch = opts->eps_branch;
   pa.tau_drift = opts->tau_drift;
+  pa.len2_min = len2_min();
   pa.fail_step = fail_step;
   pa.esc_step = out->esc_step;
   pa.meta = meta;
@@ -466,6 +493,8 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   pa.counters = counters;
   pa.Bs = B;
   pa.dlen = dlen;
+  pa.scale_ws = scale_ws;
+  pa.movable_ws = movable_ws;
   pa.block_hist = block_hist;
   pa.block_off = block_off;
   pa.perm = perm;
@@ -531,10 +560,19 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   // ---- decisions
   SimArgs sa64 = sa;
   sa64.refill_min = ctx->refill64;
+  // an FP64 pass, step by step or parallel in time
+  auto run64 = [&](const SimArgs& a, int source, bool exact, LaunchCfg cfg, bool par) -> hipError_t {
+    if (par) {
+      cfg.grid = grid_for(ctx, "par64", sim64_par_blocks_per_cu(J, source, exact, cfg.waves));
+      return launch_sim64_par(a, source, exact, cfg, st);
+    }
+    cfg.grid = grid_for(ctx, "sim64", sim64_blocks_per_cu(J, source, exact, cfg.waves, lds64));
+    return launch_sim64(a, source, exact, cfg, st);
+  };
   if (fp64) {
     c64.grid = grid_for(ctx, "sim64", sim64_blocks_per_cu(J, kFromPerm, true, c64.waves, lds64));
     if ((rc = mark(ctx, 3, st))) return rc;
-    HIP_CHECK(launch_sim64(sa64, kFromPerm, true, c64, st));
+    HIP_CHECK(run64(sa64, kFromPerm, true, c64, ctx->par64 == 2));
     ctx->ev_used[3] = true;
     ctx->last_grid32 = 0;
   } else {
@@ -550,7 +588,7 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
     if ((rc = mark(ctx, 3, st))) return rc;
     SimArgs h1 = sa64;
     h1.deesc = ctx->deesc;
-    HIP_CHECK(launch_sim64(h1, kFromEsc, ctx->exact_handover, c64, st));
+    HIP_CHECK(run64(h1, kFromEsc, ctx->exact_handover, c64, ctx->par64 >= 1 && ctx->deesc == 0));
     if (ctx->deesc > 0) {
       // the returned candidates continue in FP32 (their own counters and
       // hand-over queue), and what they hand over again is finished in FP64
@@ -587,9 +625,7 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   // written straight into its output row
   if ((rc = mark(ctx, 5, st))) return rc;
   if (opts->write != LINKS_WRITE_NONE && !(opts->write == LINKS_WRITE_VALID && out->cap == 0)) {
-    LaunchCfg cp = c64;
-    cp.grid = grid_for(ctx, "path", sim64_blocks_per_cu(J, kFromPath, fp64, cp.waves, lds64));
-    HIP_CHECK(launch_sim64(sa64, kFromPath, fp64, cp, st));
+    HIP_CHECK(run64(sa64, kFromPath, fp64, c64, ctx->par64 == 2));
     ctx->ev_used[5] = true;
   }
   if ((rc = mark(ctx, 6, st))) return rc;

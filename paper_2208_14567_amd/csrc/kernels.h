@@ -35,6 +35,7 @@ struct PrepArgs {
   int32_t pre_ratio;  // > 0: candidates whose status is not VALID keep it (low-fidelity rejects)
   int32_t out_joint;
   double eps_disc, eps_branch, tau_drift;
+  double len2_min;  // largest double whose square root is at most 1e-12 (shortest link)
   int16_t* fail_step;
   int16_t* esc_step;
   CandMeta* meta;
@@ -51,6 +52,8 @@ struct PrepArgs {
   int32_t* block_hist;   // [blocks][32]
   int32_t* block_off;    // [blocks][32]
   int32_t* perm;         // [B] candidate at each sorted position
+  double* scale_ws;      // [B] longest link of each pending candidate (count -> fill)
+  int16_t* movable_ws;   // [B] its links not between two fixed joints (count -> fill)
 };
 
 hipError_t launch_solve_order(const PrepArgs& a, hipStream_t st);
@@ -124,6 +127,9 @@ int sim64_lds_bytes(int nslot, int waves);
 // occupancy helper: resident workgroups per CU for a kernel variant
 int sim32_blocks_per_cu(int J, int mode, int T, int waves, int lds_bytes);
 int sim64_blocks_per_cu(int J, int source, bool exact, int waves, int lds_bytes);
+// the same passes computed parallel in time (16-lane segments per candidate)
+hipError_t launch_sim64_par(const SimArgs& a, int source, bool exact, const LaunchCfg& cfg, hipStream_t st);
+int sim64_par_blocks_per_cu(int J, int source, bool exact, int waves);
 
 // Path normalisation, one wave per path.
 hipError_t launch_normalize(const float* paths, int32_t P, const int32_t* count, int32_t T, int32_t mode,

@@ -123,9 +123,113 @@ __device__ bool solve_rounds(int n, const Row& r, uint32_t fixed, int tip, uint3
   return known == live_mask(n);
 }
 
+// The same three analyses with the candidate's rows held in registers (JM >= J
+// joints, rows and positions beyond the candidate's joints zero): every loop over
+// joints is unrolled, so no row is read at a run-time index, and the decisions are
+// those of structure_ok, geometry_ok and solve_rounds.
+template <int JM>
+__device__ bool reg_structure_ok(int J, int n, const uint32_t (&R)[JM], uint32_t fixed, int pivot, int tip) {
+  if (n < 3 || n > J) return false;
+  if (pivot >= n || tip >= n || pivot == tip) return false;
+  const uint32_t live = live_mask(n);
+  bool ok = (fixed & ~live) == 0u;
+  uint32_t asym = 0u;  // bit 0: some pair (i, j) linked one way only
+  uint32_t rp = 0u;    // row of the pivot
+#pragma unroll
+  for (int i = 0; i < JM; i++) {
+    const uint32_t ri = R[i];
+    if (i >= n)
+      ok &= ri == 0u;
+    else
+      ok &= (ri & ~live) == 0u && !((ri >> i) & 1u);
+#pragma unroll
+    for (int j = i + 1; j < JM; j++) asym |= (ri >> j) ^ (R[j] >> i);
+    rp = i == pivot ? ri : rp;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  ok &= (asym & 1u) == 0u;
+  ok &= ((fixed >> pivot) & 1u) && !((fixed >> tip) & 1u) && ((rp >> tip) & 1u);
+  return ok;
+}
+
+// Link lengths are compared through their squares: the square root is monotone
+// and correctly rounded, so the longest link is sqrt of the largest square, and a
+// link exceeds 1e-12 exactly when its square exceeds len2_min, the largest double
+// whose square root is at most 1e-12.  Every pair of joints is visited (no row is
+// read at a run-time index); a pair without a link contributes a square whose high
+// word is cleared, a value below 2^-1041 that never exceeds the actuator link's
+// (which a structurally valid candidate always has).
+template <int JM>
+__device__ bool reg_geometry_ok(int n, const uint32_t (&R)[JM], const double (&X)[JM], const double (&Y)[JM],
+                                uint32_t fixed, double len2_min, double* scale, int* movable) {
+  bool fin = true;
+#pragma unroll
+  for (int i = 0; i < JM; i++)
+    if (i < n) fin &= isfinite(X[i]) && isfinite(Y[i]);
+  if (!fin) return false;
+  double dmax = 0.0;
+  bool short_link = false;
+  int m = 0;
+#pragma unroll
+  for (int i = 0; i < JM; i++) {
+    const uint32_t above = R[i] & ~((2u << i) - 1u);  // links to higher joints
+    m += popc(((fixed >> i) & 1u) ? (above & ~fixed) : above);
+#pragma unroll
+    for (int j = i + 1; j < JM; j++) {
+      const bool e = (R[i] >> j) & 1u;
+      const double dx = X[i] - X[j];
+      const double dy = Y[i] - Y[j];
+      const double d2 = dx * dx + dy * dy;
+      dmax = fmax(dmax, __hiloint2double(e ? __double2hiint(d2) : 0, __double2loint(d2)));
+      short_link = short_link | (e & !(d2 > len2_min));
+    }
+    __builtin_amdgcn_sched_barrier(0);  // one row at a time: bounded register pressure
+  }
+  *scale = sqrt(dmax);
+  *movable = m;
+  return !short_link;
+}
+
+// Rounds of the graphical solver; with ord != nullptr the entries and the entry
+// index of every placed joint are stored as solve_rounds stores them.
+template <int JM>
+__device__ bool reg_solve_rounds(int n, const uint32_t (&R)[JM], uint32_t fixed, int tip, uint32_t* ord,
+                                 uint8_t* idx, int stride, int* nd_out) {
+  uint32_t known = fixed | (1u << tip);
+  int nd = 0;
+  for (;;) {
+    uint32_t now = 0u;
+#pragma unroll
+    for (int k = 0; k < JM; k++) {
+      const uint32_t kn = R[k] & known;
+      const bool place = k < n && !((known >> k) & 1u) && popc(kn) >= 2;
+      if (ord && place) {
+        const int a = lowbit(kn);
+        const int b = lowbit(kn & (kn - 1u));
+        ord[nd * stride] = (uint32_t)k | ((uint32_t)a << 8) | ((uint32_t)b << 16);
+        idx[k * stride] = (uint8_t)nd;
+      }
+      nd += place ? 1 : 0;
+      now |= place ? (1u << k) : 0u;
+    }
+    if (!now) break;
+    known |= now;
+  }
+  *nd_out = nd;
+  return known == live_mask(n);
+}
+
+// joints-per-candidate class of the register-resident kernels
+__host__ __device__ inline int jm_class(int J) {
+  return J <= 8 ? 8 : J <= 12 ? 12 : J <= 16 ? 16 : J <= 20 ? 20 : J <= 24 ? 24 : 32;
+}
+
 // Copies the workgroup's adjacency rows and initial positions into LDS, lanes
 // interleaved, with coalesced loads (the rows of consecutive candidates are
-// contiguous in memory).  Every thread of the workgroup must call it.
+// contiguous in memory).  The loads of kStageUnroll elements per lane are issued
+// together before any of them is stored.  Every thread of the workgroup must call it.
+constexpr int kStageUnroll = 8;
+
 __device__ StagedRow stage_rows(const PrepArgs& A, unsigned char* smem) {
   const int J = A.J;
   const int tid = threadIdx.x;
@@ -135,12 +239,26 @@ __device__ StagedRow stage_rows(const PrepArgs& A, unsigned char* smem) {
   double* x0_l = reinterpret_cast<double*>(smem + (size_t)J * kSortBlock * 4);  // [2J][64]
   const uint32_t* ag = A.adj + (size_t)c0 * J;
   const double2* xg = reinterpret_cast<const double2*>(A.x0 + (size_t)c0 * J * 2);
-  for (int e = tid; e < nc * J; e += kSortBlock) {
-    const int cand = e / J, i = e - cand * J;
-    adj_l[i * kSortBlock + cand] = ag[e];
-    const double2 v = xg[e];
-    x0_l[(2 * i) * kSortBlock + cand] = v.x;
-    x0_l[(2 * i + 1) * kSortBlock + cand] = v.y;
+  const int total = nc * J;  // >= 3: the workgroup holds at least one candidate
+  for (int e0 = tid; e0 < total; e0 += kStageUnroll * kSortBlock) {
+    uint32_t av[kStageUnroll];
+    double2 xv[kStageUnroll];
+#pragma unroll
+    for (int u = 0; u < kStageUnroll; ++u) {
+      const int e = min(e0 + u * kSortBlock, total - 1);  // in bounds; the extra loads are not stored
+      av[u] = ag[e];
+      xv[u] = xg[e];
+    }
+#pragma unroll
+    for (int u = 0; u < kStageUnroll; ++u) {
+      const int e = e0 + u * kSortBlock;
+      if (e < total) {
+        const int cand = e / J, i = e - cand * J;
+        adj_l[i * kSortBlock + cand] = av[u];
+        x0_l[(2 * i) * kSortBlock + cand] = xv[u].x;
+        x0_l[(2 * i + 1) * kSortBlock + cand] = xv[u].y;
+      }
+    }
   }
   __syncthreads();
   StagedRow r;
@@ -182,39 +300,62 @@ __global__ void __launch_bounds__(kPrepBlock) solve_order_kernel(PrepArgs A) {
 }
 
 // ---- simulation set-up, pass 1: status of malformed / unsolvable candidates,
-// solve-order length D of the others and a per-workgroup histogram of D.
+// solve-order length D of the others and a per-workgroup histogram of D.  The
+// rows are staged through LDS with coalesced loads and then held in registers.
+template <int JM>
 __global__ void __launch_bounds__(kSortBlock) count_kernel(PrepArgs A) {
   extern __shared__ unsigned char smem[];
-  const StagedRow row = stage_rows(A, smem);
   const int tid = threadIdx.x;
   const int c = blockIdx.x * kSortBlock + tid;
+  const bool in = c < A.B;
+  // per-candidate scalars, loaded before the rows so that the latencies overlap
+  const int n = in ? A.n[c] : 0;
+  const uint32_t fixed = in ? A.fixed[c] : 0u;
+  const int pivot = in ? A.motor[2 * c] : 0, tip = in ? A.motor[2 * c + 1] : 0;
+  const bool prev_rejected = in && A.pre_ratio > 0 && A.status[c] != 0;
+  const StagedRow row = stage_rows(A, smem);
+  const int J = A.J;
+  uint32_t R[JM];
+#pragma unroll
+  for (int i = 0; i < JM; i++) R[i] = i < J ? row.a(i) : 0u;
   int dl = 0xFF;
-  bool rejected = false;
-  if (c < A.B && A.pre_ratio > 0 && A.status[c] != 0) {
+  if (prev_rejected) {
     // rejected by the low-fidelity pass: keep its decision, on the fine grid
-    rejected = true;
     const int fs = A.fail_step[c];
     if (fs >= 0) A.fail_step[c] = (int16_t)(fs * A.pre_ratio);
     if (A.esc_step) A.esc_step[c] = -1;
     A.dlen[c] = 0xFF;
   }
-  if (c < A.B && !rejected) {
-    const int J = A.J;
-    const int n = A.n[c];
-    const uint32_t fixed = A.fixed[c];
-    const int pivot = A.motor[2 * c], tip = A.motor[2 * c + 1];
-    bool ok = structure_ok(J, n, row, fixed, pivot, tip);
+  if (in && !prev_rejected) {
+    // the decisions do not depend on one another's order: integer ones first,
+    // then the positions are read for the geometry.  Above 24 joints the rows
+    // and positions no longer fit in registers and are read from LDS.
+    bool ok = JM < 32 ? reg_structure_ok<JM>(J, n, R, fixed, pivot, tip) : structure_ok(J, n, row, fixed, pivot, tip);
+    int nd = 0;
+    bool complete = false;
+    if (ok) complete = reg_solve_rounds<JM>(n, R, fixed, tip, nullptr, nullptr, 0, &nd);
     double scale = 0.0;
     int movable = 0;
-    if (ok) ok = geometry_ok(n, row, fixed, &scale, &movable);
-    int nd = 0, depth = 0;
-    bool complete = false;
-    if (ok) complete = solve_rounds(n, row, fixed, tip, (uint32_t*)nullptr, (uint8_t*)nullptr, 0, &nd, &depth);
+    if (ok && JM == 32) {
+      ok = geometry_ok(n, row, fixed, &scale, &movable);
+    } else if (ok) {
+      double X[JM], Y[JM];
+#pragma unroll
+      for (int i = 0; i < JM; i++) {
+        X[i] = i < n ? row.x(i) : 0.0;
+        Y[i] = i < n ? row.y(i) : 0.0;
+      }
+      ok = reg_geometry_ok<JM>(n, R, X, Y, fixed, A.len2_min, &scale, &movable);
+    }
     uint8_t st = !ok ? 5 : (complete ? kPending : 4);
     A.status[c] = st;
     dl = st == kPending ? nd : 0xFF;
     A.dlen[c] = (uint8_t)dl;
-    if (st != kPending) {
+    if (st == kPending) {
+      // handed to the fill pass, which reads them at the sorted position
+      A.scale_ws[c] = scale;
+      A.movable_ws[c] = (int16_t)movable;
+    } else {
       A.fail_step[c] = -1;
       if (A.esc_step) A.esc_step[c] = -1;
     }
@@ -287,6 +428,7 @@ __global__ void __launch_bounds__(kSortBlock) rank_kernel(PrepArgs A) {
 // pass 4: the records of the candidate at every sorted position p.  Each lane
 // gathers its candidate's rows into its own LDS column, so the record writes of a
 // wave go to consecutive positions.
+template <int JM>
 __global__ void __launch_bounds__(kSortBlock) fill_kernel(PrepArgs A) {
   extern __shared__ unsigned char smem[];
   __shared__ uint32_t ord_l[kMaxJ * kSortBlock];
@@ -296,31 +438,39 @@ __global__ void __launch_bounds__(kSortBlock) fill_kernel(PrepArgs A) {
   if (p >= A.counters[kCntItems]) return;
   const int c = A.perm[p];
   const int J = A.J;
+  // the candidate's scalars and rows, every load issued before the first store
   const int n = A.n[c];
+  const uint32_t fixed = A.fixed[c];
+  const int pivot = A.motor[2 * c], tip = A.motor[2 * c + 1];
+  // scale and movable-link count as the count pass found them
+  const double scale = A.scale_ws[c];
+  const int movable = A.movable_ws[c];
+  const uint32_t* ag = A.adj + (size_t)c * J;
+  uint32_t R[JM];
+#pragma unroll
+  for (int i = 0; i < JM; i++) R[i] = ag[min(i, J - 1)];  // in the row; rows >= J cleared below
+#pragma unroll
+  for (int i = 0; i < JM; i++) R[i] = i < J ? R[i] : 0u;
   StagedRow row;
   {
-    uint32_t* adj_l = reinterpret_cast<uint32_t*>(smem);
-    double* x0_l = reinterpret_cast<double*>(smem + (size_t)J * kSortBlock * 4);
-    const uint32_t* ag = A.adj + (size_t)c * J;
-    for (int i = 0; i < J; i++) adj_l[i * kSortBlock + tid] = ag[i];
+    double* x0_l = reinterpret_cast<double*>(smem);  // [2 JM][64]
     const double2* xg = reinterpret_cast<const double2*>(A.x0 + (size_t)c * J * 2);
-    for (int i = 0; i < n; i++) {
-      const double2 v = xg[i];
-      x0_l[(2 * i) * kSortBlock + tid] = v.x;
-      x0_l[(2 * i + 1) * kSortBlock + tid] = v.y;
-    }
-    row.adj = adj_l + tid;
+    double2 xv[JM];
+#pragma unroll
+    for (int i = 0; i < JM; i++) xv[i] = xg[min(i, n - 1)];
+#pragma unroll
+    for (int i = 0; i < JM; i++)
+      if (i < n) {
+        x0_l[(2 * i) * kSortBlock + tid] = xv[i].x;
+        x0_l[(2 * i + 1) * kSortBlock + tid] = xv[i].y;
+      }
+    row.adj = nullptr;
     row.x0 = x0_l + tid;
   }
 
   const int Bs = A.Bs;
-  const uint32_t fixed = A.fixed[c];
-  const int pivot = A.motor[2 * c], tip = A.motor[2 * c + 1];
-  int nd = 0, depth = 0;
-  solve_rounds(n, row, fixed, tip, ord_l + tid, idx_l + tid, kSortBlock, &nd, &depth);
-  double scale = 0.0;
-  int movable = 0;
-  geometry_ok(n, row, fixed, &scale, &movable);
+  int nd = 0;
+  reg_solve_rounds<JM>(n, R, fixed, tip, ord_l + tid, idx_l + tid, kSortBlock, &nd);
   const int D = nd;
   // links outside the solve order: all but the actuator arm and two per placed joint
   const int redundant = movable - 1 - 2 * nd;
@@ -596,10 +746,24 @@ int prep_blocks(int32_t B) { return (B + kSortBlock - 1) / kSortBlock; }
 
 // LDS of the staged rows: adjacency [J][64] u32 and positions [2J][64] f64
 size_t staged_bytes(int J) { return (size_t)J * kSortBlock * (4 + 16); }
+// LDS of the fill pass's positions [2J][64] f64
+size_t fill_bytes(int J) { return (size_t)J * kSortBlock * 16; }
+
+template <int JM>
+void count_one(const PrepArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(count_kernel<JM>, dim3(prep_blocks(a.B)), dim3(kSortBlock), staged_bytes(a.J), st, a);
+}
 
 hipError_t launch_prep_count(const PrepArgs& a, hipStream_t st) {
   if (a.B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(count_kernel, dim3(prep_blocks(a.B)), dim3(kSortBlock), staged_bytes(a.J), st, a);
+  switch (jm_class(a.J)) {
+    case 8: count_one<8>(a, st); break;
+    case 12: count_one<12>(a, st); break;
+    case 16: count_one<16>(a, st); break;
+    case 20: count_one<20>(a, st); break;
+    case 24: count_one<24>(a, st); break;
+    default: count_one<32>(a, st); break;
+  }
   return hipGetLastError();
 }
 
@@ -614,7 +778,15 @@ hipError_t launch_prep_offsets(const PrepArgs& a, hipStream_t st) {
 hipError_t launch_prep_fill(const PrepArgs& a, hipStream_t st) {
   if (a.B <= 0) return hipSuccess;
   hipLaunchKernelGGL(rank_kernel, dim3(prep_blocks(a.B)), dim3(kSortBlock), 0, st, a);
-  hipLaunchKernelGGL(fill_kernel, dim3(prep_blocks(a.B)), dim3(kSortBlock), staged_bytes(a.J), st, a);
+  const dim3 g(prep_blocks(a.B)), b(kSortBlock);
+  switch (jm_class(a.J)) {
+    case 8: hipLaunchKernelGGL(fill_kernel<8>, g, b, fill_bytes(a.J), st, a); break;
+    case 12: hipLaunchKernelGGL(fill_kernel<12>, g, b, fill_bytes(a.J), st, a); break;
+    case 16: hipLaunchKernelGGL(fill_kernel<16>, g, b, fill_bytes(a.J), st, a); break;
+    case 20: hipLaunchKernelGGL(fill_kernel<20>, g, b, fill_bytes(a.J), st, a); break;
+    case 24: hipLaunchKernelGGL(fill_kernel<24>, g, b, fill_bytes(a.J), st, a); break;
+    default: hipLaunchKernelGGL(fill_kernel<32>, g, b, fill_bytes(a.J), st, a); break;
+  }
   return hipGetLastError();
 }
 

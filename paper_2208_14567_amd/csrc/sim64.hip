@@ -417,6 +417,424 @@ int occ_for(int J, int waves, int lds) {
   }
 }
 
+// ---- the same passes, parallel in time.
+//
+// A segment of kSeg = 16 lanes (one DPP row) holds one candidate, and lane r of the
+// segment computes step t0 - 1 + r.  Lane 0, the provider, recomputes the last step
+// already decided (or holds the starting positions), so that every other lane finds
+// its candidate's previous positions in its left neighbour.  Every dyad is placed on
+// an assumed side of its parents' line (one orientation bit per dyad, first taken
+// from the starting positions); each computing lane then applies the continuity
+// rule against its neighbour's position.  The first lane, in step order, where the
+// rule picks the other side, a placement fails or a link drifts ends the pass for
+// the segment.  Up to that lane every choice was the rule's, so the lanes computed
+// exactly what the step-by-step recurrence computes (a position depends on the
+// earlier steps only through the side chosen).  A failure is the candidate's
+// outcome at that step; a side change flips the dyad's bit and the segment
+// restarts at that step, where the rule now agrees with the bit up to that dyad (so
+// at most D restarts happen at one step).
+constexpr int kSeg = 16;
+
+// the value held by lane - 1 of the same 16-lane row (lane 0 of a row gets 0)
+__device__ __forceinline__ double row_prev(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x111, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x111, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+enum : int { kEvNone = 0, kEvLock = 1, kEvDegenerate = 2, kEvDrift = 3, kEvSide = 4 };
+
+// per-entry constants of a segment's candidate, in LDS: S, Dm and ra^2, rb^2
+// (EXACT) or Kc = (ra^2 - rb^2)/2 in A (fast)
+struct DyadC {
+  double S, Dm, A, B;
+};
+
+// LDS of the parallel pass: positions [nslot][bd] and, per segment, DMAX entries
+// of constants and their parent slots
+template <int DMAX>
+__host__ __device__ constexpr size_t par_lds_bytes(int nslot, int bd) {
+  return (size_t)nslot * bd * sizeof(double2) + (size_t)(bd / kSeg) * DMAX * (sizeof(DyadC) + sizeof(uint32_t));
+}
+
+template <int DMAX, int SRC, bool EXACT>
+__global__ void __launch_bounds__(256) simpar64_kernel(SimArgs A) {
+  extern __shared__ unsigned char smem[];
+  const int bd = blockDim.x;
+  const int tid = threadIdx.x;
+  double2* P = reinterpret_cast<double2*>(smem);  // [nslot][bd]
+  const int T = A.T;
+  const int J = A.J;
+  const int Bs = A.Bs;
+  const int lane = __lane_id();
+  const int r = lane & (kSeg - 1);    // position in the segment; 0 is the provider
+  const int seg0 = lane & ~(kSeg - 1);
+  const int segb = tid / kSeg;        // segment of the workgroup
+  DyadC* C = reinterpret_cast<DyadC*>(smem + (size_t)A.nslot * bd * sizeof(double2)) + segb * DMAX;
+  uint32_t* SL = reinterpret_cast<uint32_t*>(smem + (size_t)A.nslot * bd * sizeof(double2) +
+                                             (size_t)(bd / kSeg) * DMAX * sizeof(DyadC)) + segb * DMAX;
+  const int cnt_next = SRC == kFromEsc ? kCntEscNext : SRC == kFromPath ? kCntPathNext : kCntNext;
+  const int cnt_items = SRC == kFromEsc ? kCntEsc : SRC == kFromPath ? kCntPath : kCntItems;
+
+  // segment state (the same in every lane of a segment)
+  int cand = -1, item = 0, t0 = 0, t_end = 0, D = 0, n = 0, out_slot = 0, restarts = 0;
+  int64_t row = -1;
+  bool redundant = false;
+  bool fresh = false;             // the provider holds the starting positions
+  uint32_t ori = 0u;              // side of every dyad for the computing lanes (bit set: left of a->b)
+  uint32_t ori_prov = 0u;         // the sides in force at the provider's step
+  double px = 0, py = 0, vx = 0, vy = 0, deg_thr = 0, drift_thr = 0;
+  int dmax_w = 0;                 // largest solve order among the wave's segments
+
+  const int chunk = A.chunk;
+  int cur_base = 0, cur_left = 0;
+  bool no_more = false, exhausted = false;
+  const int nwaves = gridDim.x * (bd / kWave);
+  for (;;) {
+    // ---- segments without a candidate take the next list entries, in lane order
+    const uint64_t idle = __ballot(cand < 0 && r == 0);
+    const int nidle = __popcll(idle);
+    if (nidle == kWave / kSeg && exhausted) break;
+    if (!exhausted && nidle > 0) {
+      const int items = A.counters[cnt_items];
+      const int rank = __popcll(idle & ((1ull << seg0) - 1ull));  // idle segments before this one
+      int p = -1, given = 0;
+      for (int k = 0; k < 3 && given < nidle; ++k) {
+        if (cur_left == 0) {
+          if (no_more) break;
+          const int cur = __hip_atomic_load(&A.counters[cnt_next], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const int req = min(chunk, max(nidle - given, max(items - cur, 0) / nwaves));
+          int base = 0;
+          if (lane == 0) base = atomicAdd(&A.counters[cnt_next], req);
+          base = __shfl(base, 0);
+          cur_base = base;
+          cur_left = min(max(items - base, 0), req);
+          if (base + req >= items) no_more = true;
+        }
+        const int m = min(nidle - given, cur_left);
+        if (cand < 0 && rank >= given && rank < given + m) p = cur_base + (rank - given);
+        cur_base += m;
+        cur_left -= m;
+        given += m;
+      }
+      exhausted = no_more && cur_left == 0;
+      bool fill = false;  // this segment takes a candidate now
+      if (p >= 0) {
+        // list entry, then everything the item addresses, each level's loads issued
+        // together; the segment's lanes share the per-entry and per-slot loads
+        int it, ts = 0;
+        bool from_x0 = true;
+        if (SRC == kFromEsc) {
+          const EscEntry e = A.esc[p];
+          it = e.item;
+          ts = e.t;
+          from_x0 = e.from_x0 != 0;
+        } else if (SRC == kFromPath) {
+          it = A.path_list[p];
+        } else {
+          it = p;
+        }
+        const int c = A.perm[it];
+        const CandMeta m = A.meta[it];
+        const CandF64 f = A.cd[it];
+        int fs = -1;
+        if (SRC == kFromPath) fs = A.fail_step[c];
+        const int mD = m.D, mn = m.n;
+        // lane r: entries r and r + 16, slots r and r + 16
+        const int s0 = r, s1 = r + kSeg;
+        const int e0 = min(s0, max(mD - 1, 0)), e1 = min(s1, max(mD - 1, 0));
+        const DyadF64 q0 = A.dd[(size_t)e0 * Bs + it];
+        const DyadF64 q1 = A.dd[(size_t)e1 * Bs + it];
+        const uint32_t l0 = A.df[(size_t)e0 * Bs + it].slots;
+        const uint32_t l1 = A.df[(size_t)e1 * Bs + it].slots;
+        const int j0 = A.slot_joint[(size_t)min(s0, mn - 1) * Bs + it];
+        const int j1 = A.slot_joint[(size_t)min(s1, mn - 1) * Bs + it];
+        const double2* x0 = reinterpret_cast<const double2*>(A.x0 + (size_t)c * J * 2);
+        double2 v0 = x0[j0], v1 = x0[j1];
+        if (SRC == kFromEsc && !from_x0) {
+          const float2* dump = A.esc_pos + (size_t)p * J;
+          const float2 w0 = dump[min(s0, mn - 1)], w1 = dump[min(s1, mn - 1)];
+          if (s0 <= mD) v0 = make_double2((double)w0.x, (double)w0.y);
+          if (s1 <= mD) v1 = make_double2((double)w1.x, (double)w1.y);
+        }
+        item = it;
+        t_end = T;
+        bool take = true;
+        if (SRC == kFromPath) {
+          row = A.write_all ? (int64_t)c : (int64_t)A.path_row[c];
+          if (fs >= 0) t_end = fs;  // the path exists up to the failing step
+          take = row >= 0 && t_end > 0 && !(m.flags & kFlagNoPath);
+        }
+        if (take) {
+          cand = c;
+          D = mD;
+          n = mn;
+          out_slot = m.out_slot;
+          redundant = (m.flags & kFlagRedundant) != 0;
+          px = f.px;
+          py = f.py;
+          vx = f.vx;
+          vy = f.vy;
+          deg_thr = f.deg_thr;
+          drift_thr = f.drift_thr;
+          t0 = ts;
+          fresh = true;
+          restarts = 0;
+          fill = true;
+          if (s0 < D) {
+            C[s0] = DyadC{q0.S, q0.Dm, EXACT ? q0.ra2 : 0.5 * (q0.ra2 - q0.rb2), q0.rb2};
+            SL[s0] = l0;
+          }
+          if (s1 < D) {
+            C[s1] = DyadC{q1.S, q1.Dm, EXACT ? q1.ra2 : 0.5 * (q1.ra2 - q1.rb2), q1.rb2};
+            SL[s1] = l1;
+          }
+          // starting positions into every lane of the segment
+          for (int k = 0; k < kSeg; ++k) {
+            if (s0 < n) P[s0 * bd + tid - r + k] = v0;
+            if (s1 < n) P[s1 * bd + tid - r + k] = v1;
+          }
+        }
+      }
+      // the segment's LDS writes are complete before any lane reads them
+      __builtin_amdgcn_s_waitcnt(0xC07F);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // first guess of the sides: those of the starting positions (lane r: dyads r, r + 16)
+      bool g0 = false, g1 = false;
+      if (fill) {
+        if (r < D) {
+          const uint32_t sl = SL[r];
+          const double2 pa = P[(sl & 0xFF) * bd + tid], pb = P[((sl >> 8) & 0xFF) * bd + tid], pk = P[r * bd + tid];
+          g0 = (pb.x - pa.x) * (pk.y - pa.y) - (pb.y - pa.y) * (pk.x - pa.x) >= 0.0;
+        }
+        if (r + kSeg < D) {
+          const uint32_t sl = SL[r + kSeg];
+          const double2 pa = P[(sl & 0xFF) * bd + tid], pb = P[((sl >> 8) & 0xFF) * bd + tid];
+          const double2 pk = P[(r + kSeg) * bd + tid];
+          g1 = (pb.x - pa.x) * (pk.y - pa.y) - (pb.y - pa.y) * (pk.x - pa.x) >= 0.0;
+        }
+      }
+      const uint64_t b0 = __ballot(g0), b1 = __ballot(g1);
+      if (fill) {
+        ori = (uint32_t)((b0 >> seg0) & 0xFFFFu) | ((uint32_t)((b1 >> seg0) & 0xFFFFu) << kSeg);
+        ori_prov = ori;
+      }
+      // largest solve order among the wave's segments (bounds the dyad loop)
+      int dm = cand >= 0 ? D : 0;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) dm = max(dm, __shfl_xor(dm, off));
+      dmax_w = dm;
+    }
+    if (__ballot(cand >= 0) == 0ull) continue;
+
+    // ---- one pass: lane r computes step t
+    const int t = t0 - 1 + r;
+    const bool comp = cand >= 0 && t < t_end && !(r == 0 && fresh);
+    const uint32_t side = r == 0 ? ori_prov : ori;
+    if (comp) {
+      const double2 cs = A.cs64[t];
+      const double ct = cs.x, st = cs.y;
+      if (EXACT)
+        P[D * bd + tid] = make_double2(px + (ct * vx - st * vy), py + (st * vx + ct * vy));
+      else
+        P[D * bd + tid] = make_double2(fma(ct, vx, fma(-st, vy, px)), fma(st, vx, fma(ct, vy, py)));
+    }
+    int ev = kEvNone, ev_s = 0;
+#pragma unroll
+    for (int s = 0; s < DMAX; ++s) {
+      if (s < dmax_w) {
+        const bool act = comp && s < D && ev == kEvNone;
+        double2 val = P[s * bd + tid];
+        // EXACT: both intersections; fast: base point and offset
+        double rx0 = 0, ry0 = 0, rx1 = 0, ry1 = 0;
+        bool placed = false;
+        if (act) {
+          const uint32_t sl = SL[s];
+          const DyadC q = C[s];
+          const int a = sl & 0xFF, b = (sl >> 8) & 0xFF;
+          const double2 pa = P[a * bd + tid];
+          const double2 pb = P[b * bd + tid];
+          const double dx = pb.x - pa.x;
+          const double dy = pb.y - pa.y;
+          const bool left = (side >> s) & 1u;
+          if (EXACT) {
+            const double d2 = dx * dx + dy * dy;
+            if (d2 <= deg_thr) {
+              ev = kEvDegenerate;
+            } else {
+              const double K = (q.S - d2) * (d2 - q.Dm);
+              if (K < 0.0) {
+                ev = kEvLock;
+              } else {
+                const double d = sqrt(d2);
+                const double h = sqrt(K) / (2.0 * d);
+                const double along = (d2 + q.A - q.B) / (2.0 * d);
+                const double bx = pa.x + (along / d) * dx;
+                const double by = pa.y + (along / d) * dy;
+                const double ox = -(h / d) * dy;
+                const double oy = (h / d) * dx;
+                rx0 = bx + ox;
+                ry0 = by + oy;
+                rx1 = bx - ox;
+                ry1 = by - oy;
+                val = left ? make_double2(rx0, ry0) : make_double2(rx1, ry1);
+                placed = true;
+              }
+            }
+          } else {
+            const double d2 = fma(dy, dy, dx * dx);
+            const double K = (q.S - d2) * (d2 - q.Dm);
+            if (d2 <= deg_thr) {
+              ev = kEvDegenerate;
+            } else if (K < 0.0) {
+              ev = kEvLock;
+            } else {
+              const double rd = rsqrt_nr(d2);
+              const double inv = rd * rd;
+              const double Kp = fmax(K, 1e-300);
+              const double sK = Kp * rsqrt_nr(Kp);
+              const double al = fma(q.A, inv, 0.5);
+              const double be = sK * (0.5 * inv);
+              rx0 = fma(al, dx, pa.x);
+              ry0 = fma(al, dy, pa.y);
+              rx1 = -be * dy;
+              ry1 = be * dx;
+              const double sgn = left ? 1.0 : -1.0;
+              val = make_double2(fma(sgn, rx1, rx0), fma(sgn, ry1, ry0));
+              placed = true;
+            }
+          }
+          if (placed) P[s * bd + tid] = val;
+        }
+        // the previous step's position of this joint, from the left neighbour
+        const double qx = row_prev(val.x), qy = row_prev(val.y);
+        if (placed && r > 0) {
+          bool rule_left;
+          if (EXACT) {
+            const double dp2 = (qx - rx0) * (qx - rx0) + (qy - ry0) * (qy - ry0);
+            const double dm2 = (qx - rx1) * (qx - rx1) + (qy - ry1) * (qy - ry1);
+            rule_left = dp2 <= dm2;
+          } else {
+            rule_left = fma(qx - rx0, rx1, (qy - ry0) * ry1) >= 0.0;
+          }
+          if (rule_left != (((side >> s) & 1u) != 0u)) {
+            ev = kEvSide;
+            ev_s = s;
+          }
+        }
+      }
+    }
+    if (comp && r > 0 && ev == kEvNone && redundant && drift_check(A, cand, item, D, n, P, bd, tid, drift_thr))
+      ev = kEvDrift;
+
+    // ---- the segment's first event, in step order
+    const uint64_t evb = __ballot(comp && r > 0 && ev != kEvNone);
+    const uint32_t segm = (uint32_t)(evb >> seg0) & 0xFFFFu;
+    const int f = segm ? __ffs(segm) - 1 : kSeg;
+    const int info = __shfl(ev | (ev_s << 8), seg0 + (f < kSeg ? f : 0));
+    const int kind = f < kSeg ? (info & 0xFF) : kEvNone;
+    if (SRC == kFromPath && comp && r > 0 && r < f) {
+      const double2 po = P[out_slot * bd + tid];
+      if (A.path_f64)
+        reinterpret_cast<double2*>(A.path)[row * T + t] = po;
+      else
+        reinterpret_cast<float2*>(A.path)[row * T + t] = make_float2((float)po.x, (float)po.y);
+    }
+    if (cand >= 0) {
+      bool done = false;
+      const int te = t0 - 1 + f;  // step of the event
+      if (kind == kEvNone) {
+        const int next = t0 + (kSeg - 1);
+        if (next >= t_end) {
+          if (SRC != kFromPath && r == 0) {
+            A.status[cand] = 0;
+            A.fail_step[cand] = -1;
+            if (SRC == kFromPerm && A.esc_step) A.esc_step[cand] = -1;
+          }
+          done = true;
+        } else {
+          t0 = next;
+          ori_prov = ori;
+          fresh = false;
+          restarts = 0;
+        }
+      } else if (kind == kEvSide) {
+        // the provider of the restarted pass is the step before the change
+        if (f >= 2) {
+          ori_prov = ori;
+          fresh = false;
+          restarts = 0;
+        }
+        ori ^= 1u << (info >> 8);
+        t0 = te;
+        if (++restarts > D + 1) {
+          // cannot happen (each restart at one step moves the first change to a
+          // later dyad); the candidate is left without a final status
+          if (SRC != kFromPath && r == 0) A.status[cand] = kPending;
+          done = true;
+        }
+      } else {
+        if (SRC == kFromPath) {
+          // a failure here (possible only within rounding of a threshold) leaves the
+          // rest of the row NaN
+          const double nan = __builtin_nan("");
+          for (int tt = te + r; tt < t_end; tt += kSeg) {
+            if (A.path_f64)
+              reinterpret_cast<double2*>(A.path)[row * T + tt] = make_double2(nan, nan);
+            else
+              reinterpret_cast<float2*>(A.path)[row * T + tt] = make_float2((float)nan, (float)nan);
+          }
+        } else if (r == 0) {
+          A.status[cand] = (uint8_t)kind;
+          A.fail_step[cand] = (int16_t)te;
+          if (SRC == kFromPerm && A.esc_step) A.esc_step[cand] = -1;
+        }
+        done = true;
+      }
+      if (done) cand = -1;
+    }
+  }
+}
+
+template <int DMAX, int SRC, bool EXACT>
+void launch_par_one(const SimArgs& a, const LaunchCfg& cfg, hipStream_t st) {
+  const int bd = cfg.waves * kWave;
+  const size_t lds = par_lds_bytes<DMAX>(a.nslot, bd);
+  hipLaunchKernelGGL((simpar64_kernel<DMAX, SRC, EXACT>), dim3(cfg.grid), dim3(bd), lds, st, a);
+}
+
+template <int SRC, bool EXACT>
+hipError_t dispatch_par(const SimArgs& a, const LaunchCfg& cfg, hipStream_t st) {
+  switch (sim32_dmax(a.J)) {
+    case 5: launch_par_one<5, SRC, EXACT>(a, cfg, st); break;
+    case 11: launch_par_one<11, SRC, EXACT>(a, cfg, st); break;
+    case 18: launch_par_one<18, SRC, EXACT>(a, cfg, st); break;
+    default: launch_par_one<30, SRC, EXACT>(a, cfg, st); break;
+  }
+  return hipGetLastError();
+}
+
+template <int DMAX, int SRC, bool EXACT>
+int occ_par(int J, int waves) {
+  const int lds = (int)par_lds_bytes<DMAX>(J, waves * kWave);
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, simpar64_kernel<DMAX, SRC, EXACT>, waves * kWave, lds) !=
+      hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
+}
+
+template <int SRC, bool EXACT>
+int occ_par_for(int J, int waves) {
+  switch (sim32_dmax(J)) {
+    case 5: return occ_par<5, SRC, EXACT>(J, waves);
+    case 11: return occ_par<11, SRC, EXACT>(J, waves);
+    case 18: return occ_par<18, SRC, EXACT>(J, waves);
+    default: return occ_par<30, SRC, EXACT>(J, waves);
+  }
+}
+
 }  // namespace
 
 int sim64_lds_bytes(int nslot, int waves) { return nslot * waves * kWave * (int)sizeof(double2); }
@@ -448,6 +866,36 @@ int sim64_blocks_per_cu(int J, int source, bool exact, int waves, int lds) {
     case kFromEsc: return occ_for<kFromEsc, false>(J, waves, lds);
     case kFromPath: return occ_for<kFromPath, false>(J, waves, lds);
     default: return occ_for<kFromPerm, false>(J, waves, lds);
+  }
+}
+
+hipError_t launch_sim64_par(const SimArgs& a, int source, bool exact, const LaunchCfg& cfg, hipStream_t st) {
+  if (exact) {
+    switch (source) {
+      case kFromEsc: return dispatch_par<kFromEsc, true>(a, cfg, st);
+      case kFromPath: return dispatch_par<kFromPath, true>(a, cfg, st);
+      default: return dispatch_par<kFromPerm, true>(a, cfg, st);
+    }
+  }
+  switch (source) {
+    case kFromEsc: return dispatch_par<kFromEsc, false>(a, cfg, st);
+    case kFromPath: return dispatch_par<kFromPath, false>(a, cfg, st);
+    default: return dispatch_par<kFromPerm, false>(a, cfg, st);
+  }
+}
+
+int sim64_par_blocks_per_cu(int J, int source, bool exact, int waves) {
+  if (exact) {
+    switch (source) {
+      case kFromEsc: return occ_par_for<kFromEsc, true>(J, waves);
+      case kFromPath: return occ_par_for<kFromPath, true>(J, waves);
+      default: return occ_par_for<kFromPerm, true>(J, waves);
+    }
+  }
+  switch (source) {
+    case kFromEsc: return occ_par_for<kFromEsc, false>(J, waves);
+    case kFromPath: return occ_par_for<kFromPath, false>(J, waves);
+    default: return occ_par_for<kFromPerm, false>(J, waves);
   }
 }
 

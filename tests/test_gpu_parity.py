@@ -101,6 +101,55 @@ def test_status_fixtures(ctx, L, precision):
         assert np.allclose(r["path"], ref["path"], rtol=0, atol=tol, equal_nan=True)
 
 
+def test_parallel_in_time_fp64_passes(ctx, L):
+    """Every FP64 pass computed parallel in time gives the step-by-step results
+    bit for bit (statuses, steps and paths), in both precisions."""
+    _say("[par64]")
+    b = gen.workload("dyad_4_20", 20000, seed=21)
+    db = L.to_device(b)
+    res = {}
+    try:
+        for mode in (0, 1, 2):
+            ctx.set_option("par64", mode)
+            for precision in (L.FP64, L.FP32_RECHECK):
+                r = _np(ctx.simulate(db, T=200, precision=precision, write=L.WRITE_ALL, path_dtype=L.F64))
+                res[mode, precision] = r
+    finally:
+        ctx.set_option("par64", 1)
+    for precision in (L.FP64, L.FP32_RECHECK):
+        for mode in (1, 2):
+            a, z = res[0, precision], res[mode, precision]
+            for k in ("status", "fail_step", "esc_step"):
+                assert np.array_equal(a[k], z[k]), (precision, mode, k)
+            assert np.array_equal(a["path"], z["path"], equal_nan=True), (precision, mode)
+    ref = oracle.simulate(b, T=200, path=True, nthreads=NTH)
+    z = res[2, L.FP64]
+    assert np.array_equal(z["status"], ref["status"]) and np.array_equal(z["fail_step"], ref["fail_step"])
+    assert np.array_equal(z["path"], ref["path"], equal_nan=True)
+
+
+@pytest.mark.parametrize("J", [7, 10, 13, 20, 22, 32])
+def test_malformed_candidates(ctx, L, J):
+    """Every way of breaking the input contract, mixed into valid batches of each
+    joint-stride class: statuses and failure steps as the oracle's."""
+    _say(f"[malformed] J={J}")
+    b = gen.dyad_batch(3000, 300 + J, gen.n_uniform(4, J), J=J)
+    m, kinds = mech.malform(b, seed=J)
+    ref = oracle.simulate(m, T=50, nthreads=NTH)
+    for precision in (L.FP64, L.FP32_RECHECK):
+        r = _np(ctx.simulate(L.to_device(m), T=50, precision=precision))
+        # the set-up decides UNSOLVABLE and BAD_MECH exactly in both precisions
+        pre = np.isin(ref["status"], (oracle.UNSOLVABLE, oracle.BAD_MECH)) | np.isin(r["status"], (4, 5))
+        bad = pre & (r["status"] != ref["status"])
+        if precision == L.FP64:
+            bad |= r["status"] != ref["status"]
+        assert not bad.any(), (precision, [mech.MALFORM_KINDS[k] for k in kinds[bad][:5]])
+        if precision == L.FP64:
+            assert np.array_equal(r["fail_step"], ref["fail_step"])
+    _, _, _, st = ctx.solve_order(L.to_device(m))
+    assert np.array_equal(st.cpu().numpy(), oracle.solve_order(m)[3])
+
+
 @pytest.mark.parametrize("name,B,seed", WORKLOADS)
 def test_fp64_bit_exact(ctx, L, name, B, seed):
     _say(f"[fp64] {name} B={B}")
