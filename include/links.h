@@ -205,7 +205,10 @@ int links_set_tuning(links_ctx* ctx, int waves32, int refill_min, int waves64);
  *                     assumed side, checked against the continuity rule and
  *                     restarted where the rule changes side (results identical to
  *                     the step-by-step pass).  0: none; 1 (default): the hand-over
- *                     pass (whose long FP64 runs are few); 2: every FP64 pass. */
+ *                     pass (whose long FP64 runs are few); 2: every FP64 pass;
+ *   "par32"           1: the FP32 pass runs parallel in time the same way (same
+ *                     decisions and hand-over steps as the step-by-step pass);
+ *                     0 (default).  Ignored when "deesc" > 0. */
 int links_set_option(links_ctx* ctx, const char* name, int value);
 /* Current value of a named option in *value (LINKS_ERR_ARG for an unknown name). */
 int links_get_option(links_ctx* ctx, const char* name, int* value);

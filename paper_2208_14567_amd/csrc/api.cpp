@@ -72,6 +72,10 @@ struct links_ctx {
   // 0 none, 1 the hand-over pass, 2 every FP64 pass.  The return to FP32 after a
   // hand-over (deesc > 0) keeps the step-by-step pass.
   int par64 = 1;
+  // the FP32 pass computed parallel in time (with deesc > 0 the step-by-step pass);
+  // off by default: its larger LDS footprint per wave costs more than the idle
+  // lanes it saves on the measured workloads
+  bool par32 = false;
   std::map<std::string, int> occ_cache;
   // last call's statistics
   int last_grid32 = 0, last_grid64 = 0;
@@ -281,6 +285,11 @@ int links_set_option(links_ctx* ctx, const char* name, int value) {
     ctx->exact_handover = value != 0;
     return LINKS_OK;
   }
+  if (k == "par32") {
+    if (value != 0 && value != 1) return fail(LINKS_ERR_ARG, "par32 must be 0 or 1");
+    ctx->par32 = value != 0;
+    return LINKS_OK;
+  }
   if (k == "par64") {
     if (value < 0 || value > 2) return fail(LINKS_ERR_ARG, "par64 must be 0, 1 or 2");
     ctx->par64 = value;
@@ -301,6 +310,7 @@ int links_get_option(links_ctx* ctx, const char* name, int* value) {
   else if (k == "deesc") *value = ctx->deesc;
   else if (k == "exact_handover") *value = ctx->exact_handover ? 1 : 0;
   else if (k == "par64") *value = ctx->par64;
+  else if (k == "par32") *value = ctx->par32 ? 1 : 0;
   else return fail(LINKS_ERR_ARG, "unknown option '%s'", name);
   return LINKS_OK;
 }
@@ -549,6 +559,7 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   sa.res = res;
   sa.res_pos = res_pos;
   sa.deesc = 0;
+  sa.esc_by_item = 0;
   sa.resume = 0;
   sa.chunk = ctx->chunk;
 
@@ -580,14 +591,20 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
     c32.waves = ctx->waves32;
     c32.refill_min = ctx->refill_min;
     const int mode = opts->precision == LINKS_FP32_ONLY ? 1 : 0;
-    const int lds32 = sim32_lds_bytes(J, c32.waves, T);
-    c32.grid = grid_for(ctx, "sim32", sim32_blocks_per_cu(J, mode, T, c32.waves, lds32));
-    HIP_CHECK(launch_sim32(sa, mode, c32, st));
+    if (ctx->par32 && ctx->deesc == 0) {
+      c32.grid = grid_for(ctx, "par32", sim32_par_blocks_per_cu(J, mode, T, c32.waves));
+      HIP_CHECK(launch_sim32_par(sa, mode, c32, st));
+    } else {
+      const int lds32 = sim32_lds_bytes(J, c32.waves, T);
+      c32.grid = grid_for(ctx, "sim32", sim32_blocks_per_cu(J, mode, T, c32.waves, lds32));
+      HIP_CHECK(launch_sim32(sa, mode, c32, st));
+    }
     ctx->ev_used[2] = true;
     c64.grid = grid_for(ctx, "sim64", sim64_blocks_per_cu(J, kFromEsc, ctx->exact_handover, c64.waves, lds64));
     if ((rc = mark(ctx, 3, st))) return rc;
     SimArgs h1 = sa64;
     h1.deesc = ctx->deesc;
+    h1.esc_by_item = ctx->par32 && ctx->deesc == 0 ? 1 : 0;  // the parallel FP32 pass dumps by item
     HIP_CHECK(run64(h1, kFromEsc, ctx->exact_handover, c64, ctx->par64 >= 1 && ctx->deesc == 0));
     if (ctx->deesc > 0) {
       // the returned candidates continue in FP32 (their own counters and

@@ -113,6 +113,9 @@ struct LaunchCfg {
 };
 // FP32 pass: mode 0 escalates to FP64, mode 1 never escalates.
 hipError_t launch_sim32(const SimArgs& a, int mode, const LaunchCfg& cfg, hipStream_t st);
+// the FP32 pass computed parallel in time (16-lane segments per candidate)
+hipError_t launch_sim32_par(const SimArgs& a, int mode, const LaunchCfg& cfg, hipStream_t st);
+int sim32_par_blocks_per_cu(int J, int mode, int T, int waves);
 int sim32_lds_bytes(int nslot, int waves, int T);
 constexpr int kTableLds = 1024;  // crank tables up to this many steps live in LDS
 int sim32_dmax(int J);

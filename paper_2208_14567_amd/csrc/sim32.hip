@@ -411,6 +411,438 @@ int occ(int waves, int lds) {
   return nb > 0 ? nb : 1;
 }
 
+// ---- the FP32 pass, parallel in time.
+//
+// A segment of 16 lanes (one DPP row) holds one candidate; lane r computes step
+// t0 - 1 + r, lane 0 (the provider) recomputing the last decided step or holding
+// the reference positions, so that each lane finds the previous step's positions
+// and error bounds of its candidate in its left neighbour.  Every dyad is placed
+// on an assumed side of its parents' line and each computing lane takes the
+// decisions of the step-by-step pass (band, lock, branch side) against its
+// neighbour's values.  The first lane in step order with a band, a lock or a
+// side different from the assumed one ends the pass for the segment: a band hands
+// the candidate to FP64 at that step (with the previous step's positions), a lock
+// is its outcome, a side change flips the dyad's side and restarts the segment at
+// that step.  Lanes before it computed what the step-by-step pass computes.
+constexpr int kSeg32 = 16;
+
+__device__ __forceinline__ int row_prev_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false); }
+__device__ __forceinline__ float row_prev_f(float v) { return __int_as_float(row_prev_i(__float_as_int(v))); }
+
+enum : int { kE32None = 0, kE32Lock = 1, kE32Degenerate = 2, kE32Band = 3, kE32Side = 4 };
+
+// LDS: positions [nslot][bd] f32x2 and error bounds [nslot][bd] u16; per segment
+// two tables of DMAX entries (S, Dm, Kc, parent slots: the live candidate's and the
+// next one's), the next candidate's reference positions [32], CandF32 [16] and
+// meta, index and sorted position; the crank table when it fits.
+template <int DMAX>
+__host__ __device__ constexpr size_t par32_seg_bytes() {
+  return 2 * DMAX * sizeof(float4) + 32 * sizeof(float2) + 16 * sizeof(float) + 4 * sizeof(int);
+}
+
+template <int DMAX>
+__host__ __device__ constexpr size_t par32_lds_bytes(int nslot, int bd, int T) {
+  return (size_t)nslot * bd * (sizeof(float2) + sizeof(uint16_t)) + (size_t)(bd / kSeg32) * par32_seg_bytes<DMAX>() +
+         (T <= kTableLds ? (size_t)T * sizeof(float2) : 0);
+}
+
+template <int DMAX, int MODE>
+__global__ void __launch_bounds__(256) simpar32_kernel(SimArgs A) {
+  extern __shared__ unsigned char smem[];
+  const int bd = blockDim.x;
+  const int tid = threadIdx.x;
+  float2* P = reinterpret_cast<float2*>(smem);                            // [nslot][bd]
+  uint16_t* E = reinterpret_cast<uint16_t*>(P + (size_t)A.nslot * bd);    // [nslot][bd]
+  unsigned char* segs = reinterpret_cast<unsigned char*>(E + (size_t)A.nslot * bd);
+  unsigned char* seg = segs + (size_t)(tid / kSeg32) * par32_seg_bytes<DMAX>();
+  float4* Ct = reinterpret_cast<float4*>(seg);                      // [2][DMAX]
+  float2* PN = reinterpret_cast<float2*>(seg + 2 * DMAX * sizeof(float4));  // [32]
+  float* CFN = reinterpret_cast<float*>(PN + 32);                   // [16]
+  int* MCN = reinterpret_cast<int*>(CFN + 16);                      // meta, index, sorted position
+  constexpr bool tab_lds = (MODE & 2) == 0;
+  float2* tab = reinterpret_cast<float2*>(segs + (size_t)(bd / kSeg32) * par32_seg_bytes<DMAX>());
+  const int T = A.T;
+  const int J = A.J;
+  const int Bs = A.Bs;
+  if (tab_lds) {
+    for (int i = tid; i < T; i += bd) tab[i] = A.cs32[i];
+    __syncthreads();
+  }
+  const int lane = __lane_id();
+  const int r = lane & (kSeg32 - 1);
+  const int seg0 = lane & ~(kSeg32 - 1);
+
+  // segment state (the same in every lane of a segment)
+  int cand = -1, item = 0, t0 = 0, D = 0, n = 0, restarts = 0;
+  bool fresh = false, force64 = false;
+  int cpar = 0;                   // which entry table holds the live candidate
+  uint32_t ori = 0u, ori_prov = 0u;
+  float px = 0.f, py = 0.f, vx = 0.f, vy = 0.f, U = 0.f, KB = 0.f, CD = 0.f, EB = 0.f;
+  float U2 = 0.f, TS = 0.f, uu = 0.f, DG = 0.f;
+  int dmax_w = 0;
+  // next candidate: claimed (need_next false), loaded into registers during a
+  // pass (in_flight), then staged in LDS (has_staged) until the segment is free
+  bool need_next = true, in_flight = false, has_staged = false;
+  int pf_p = 0, pf_c = 0;
+  uint32_t pf_meta = 0u;
+  float pf_cf = 0.f;
+  DyadF32 pf_q0, pf_q1;
+  float2 pf_w0 = make_float2(0.f, 0.f), pf_w1 = make_float2(0.f, 0.f);
+  pf_q0.S = pf_q0.Dm = pf_q0.Kc = 0.f;
+  pf_q0.slots = 0u;
+  pf_q1 = pf_q0;
+  // hand-over queue entry whose index (an atomic's result) is read one pass later
+  bool esc_pend = false;
+  int esc_i = 0, esc_item = 0, esc_te = 0;
+
+  const int chunk = A.chunk;
+  int cur_base = 0, cur_left = 0;
+  bool no_more = false, exhausted = false;
+  const int nwaves = gridDim.x * (bd / kWave);
+  const int items = A.counters[kCntItems];
+  for (;;) {
+    // ---- 1. free segments take up their staged candidate (LDS only)
+    asm volatile("" ::: "memory");
+    const bool fill = cand < 0 && has_staged;
+    if (__ballot(fill) != 0ull) {
+      if (fill) {
+        const uint32_t mp = (uint32_t)MCN[0];
+        cand = MCN[1];
+        item = MCN[2];
+        D = mp & 0xFF;
+        n = (mp >> 8) & 0xFF;
+        force64 = ((mp >> 24) & kFlagRedundant) != 0;  // drift checks run in the FP64 pass
+        px = CFN[0];
+        py = CFN[1];
+        vx = CFN[2];
+        vy = CFN[3];
+        U = CFN[4];
+        KB = CFN[5];
+        CD = CFN[6];
+        EB = CFN[7];
+        U2 = CFN[8];
+        TS = CFN[9];
+        uu = CFN[10];
+        DG = CFN[11];
+        cpar ^= 1;
+        t0 = 0;
+        fresh = true;
+        restarts = 0;
+        has_staged = false;
+        need_next = true;
+#pragma unroll
+        for (int sl = 0; sl < DMAX + 2; ++sl)
+          if (sl < n) {
+            const float2 v = PN[sl];
+            P[sl * bd + tid] = v;
+            E[sl * bd + tid] = bound_up(uu * (fabsf(v.x) + fabsf(v.y)));  // rounding of x0 to FP32
+          }
+      }
+      __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): LDS operations of a wave complete in order
+      asm volatile("" ::: "memory");
+      // first guess of the sides: those of the reference positions
+      const float4* C = Ct + cpar * DMAX;
+      bool g0 = false, g1 = false;
+      if (fill) {
+        if (r < D) {
+          const uint32_t sl = __float_as_uint(C[r].w);
+          const float2 pa = P[(sl & 0xFF) * bd + tid], pb = P[((sl >> 8) & 0xFF) * bd + tid], pk = P[r * bd + tid];
+          g0 = (pb.x - pa.x) * (pk.y - pa.y) - (pb.y - pa.y) * (pk.x - pa.x) >= 0.f;
+        }
+        if (r + kSeg32 < D) {
+          const uint32_t sl = __float_as_uint(C[r + kSeg32].w);
+          const float2 pa = P[(sl & 0xFF) * bd + tid], pb = P[((sl >> 8) & 0xFF) * bd + tid];
+          const float2 pk = P[(r + kSeg32) * bd + tid];
+          g1 = (pb.x - pa.x) * (pk.y - pa.y) - (pb.y - pa.y) * (pk.x - pa.x) >= 0.f;
+        }
+      }
+      const uint64_t gb0 = __ballot(g0), gb1 = __ballot(g1);
+      if (fill) {
+        ori = (uint32_t)((gb0 >> seg0) & 0xFFFFu) | ((uint32_t)((gb1 >> seg0) & 0xFFFFu) << kSeg32);
+        ori_prov = ori;
+      }
+      int dm = cand >= 0 ? D : 0;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) dm = max(dm, __shfl_xor(dm, off));
+      dmax_w = dm;
+    }
+    if (__ballot(r == 0 && (cand >= 0 || has_staged || in_flight)) == 0ull && exhausted) {
+      if (esc_pend && r == 0) {
+        EscEntry e;
+        e.item = esc_item;
+        e.t = (int16_t)esc_te;
+        e.from_x0 = esc_te == 0 ? 1 : 0;
+        e.pad = 0;
+        A.esc[esc_i] = e;
+      }
+      break;
+    }
+
+    // ---- 2. claim the next candidate of segments that need one and issue its loads
+    {
+      const uint64_t want = __ballot(need_next && r == 0 && !exhausted);
+      const int nwant = __popcll(want);
+      if (nwant > 0) {
+        const int rank = __popcll(want & ((1ull << seg0) - 1ull));
+        int p = -1, given = 0;
+        for (int k = 0; k < 3 && given < nwant; ++k) {
+          if (cur_left == 0) {
+            if (no_more) break;
+            const int cur = __hip_atomic_load(&A.counters[kCntNext], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int req = min(chunk, max(nwant - given, max(items - cur, 0) / nwaves));
+            int base = 0;
+            if (lane == 0) base = atomicAdd(&A.counters[kCntNext], req);
+            base = __shfl(base, 0);
+            cur_base = base;
+            cur_left = min(max(items - base, 0), req);
+            if (base + req >= items) no_more = true;
+          }
+          const int m = min(nwant - given, cur_left);
+          if (need_next && rank >= given && rank < given + m) p = cur_base + (rank - given);
+          cur_base += m;
+          cur_left -= m;
+          given += m;
+        }
+        exhausted = no_more && cur_left == 0;
+        if (need_next) {
+          need_next = false;
+          if (p >= 0) {
+            in_flight = true;
+            pf_p = p;
+            pf_c = A.perm[p];
+            pf_meta = reinterpret_cast<const uint32_t*>(A.meta)[p];
+            pf_cf = reinterpret_cast<const float*>(A.cf + p)[r];
+            // rows beyond the candidate's are loaded but not used (the record
+            // arrays have J rows)
+            const int s0 = min(r, J - 1), s1 = min(r + kSeg32, J - 1);
+            pf_q0 = A.df[(size_t)s0 * Bs + p];
+            pf_q1 = A.df[(size_t)s1 * Bs + p];
+            pf_w0 = A.x0s[(size_t)s0 * Bs + p];
+            pf_w1 = A.x0s[(size_t)s1 * Bs + p];
+          }
+        }
+      }
+    }
+
+    // ---- 3. one pass: lane r computes step t
+    const float4* C = Ct + cpar * DMAX;
+    const int t = t0 - 1 + r;
+    const bool comp = cand >= 0 && !force64 && t < T && !(r == 0 && fresh);
+    const uint32_t side = r == 0 ? ori_prov : ori;
+    int ev = kE32None, ev_s = 0;
+    if (__ballot(cand >= 0 && !force64) != 0ull) {
+      if (comp) {
+        const float2 cs = tab_lds ? tab[t] : A.cs32[t];
+        P[D * bd + tid] = make_float2(fmaf(cs.x, vx, fmaf(-cs.y, vy, px)), fmaf(cs.y, vx, fmaf(cs.x, vy, py)));
+        E[D * bd + tid] = bound_up(U);
+      }
+#pragma unroll
+      for (int s = 0; s < DMAX; ++s) {
+        if (s < dmax_w) {
+          const bool act = comp && s < D && ev == kE32None;
+          float2 val = P[s * bd + tid];
+          uint16_t vb = E[s * bd + tid];
+          float bx = 0.f, by = 0.f, ox = 0.f, oy = 0.f, h = 0.f, Eab = 0.f, rd = 0.f;
+          bool bK = false, lock = false, deg = false;
+          bool left = false;
+          if (act) {
+            const float4 q = C[s];
+            const uint32_t sl = __float_as_uint(q.w);
+            const int a = sl & 0xFF, b = (sl >> 8) & 0xFF;
+            const float2 pa = P[a * bd + tid];
+            const float2 pb = P[b * bd + tid];
+            const float dx = pb.x - pa.x, dy = pb.y - pa.y;
+            const float d2 = fmaf(dy, dy, dx * dx);
+            const float S = q.x, Dm = q.y;
+            const float K = (S - d2) * (d2 - Dm);
+            rd = rsq(d2);
+            const float inv = rd * rd;
+            const float Kp = fmaxf(K, 1e-30f);
+            const float rK = rsq(Kp);
+            const float sK = Kp * rK;
+            const float be = sK * (0.5f * inv);
+            const float al = fmaf(q.z, inv, 0.5f);
+            bx = fmaf(al, dx, pa.x);
+            by = fmaf(al, dy, pa.y);
+            ox = -be * dy;
+            oy = be * dx;
+            left = (side >> s) & 1u;
+            const float sgn = left ? 1.f : -1.f;
+            val = make_float2(fmaf(sgn, ox, bx), fmaf(sgn, oy, by));
+            P[s * bd + tid] = val;
+            lock = K < 0.f;
+            if ((MODE & 1) == 0) {
+              const float Ea = bound_f(E[a * bd + tid]);
+              const float Eb = bound_f(E[b * bd + tid]);
+              Eab = Ea + Eb;
+              const float d = d2 * rd;
+              h = 0.5f * sK * rd;
+              const float sensK = 4.f * d * fabsf(fmaf(0.5f, S + Dm, -d2));
+              const float kthr = fmaf(sensK, Eab, KB);
+              bK = (fabsf(K) < kthr) | (d2 < CD);
+              const float A2 = 0.5f * (S - Dm) * rK;  // 2 ra rb / sqrt(K)
+              vb = bound_up(A2 * (Eab + fmaf(uu, fabsf(pa.x) + fabsf(pa.y), U2)));
+              E[s * bd + tid] = vb;
+            } else {
+              deg = d2 <= DG;
+            }
+          }
+          // the previous step's position of this joint and its bound, from the left
+          // neighbour
+          const float qx = row_prev_f(val.x), qy = row_prev_f(val.y);
+          const float Ep = (MODE & 1) == 0 ? bound_f((uint16_t)row_prev_i((int)vb)) : 0.f;
+          if (act && r > 0) {
+            const float sg = fmaf(qx - bx, ox, (qy - by) * oy);
+            const bool rule_left = sg >= 0.f;
+            if ((MODE & 1) == 0) {
+              const float mthr = fmaf(Eab, fmaf(TS, rd, 1.f), EB + Ep);
+              const bool band = bK | (fabsf(sg) < mthr * h);
+              ev = band ? kE32Band : lock ? kE32Lock : rule_left != left ? kE32Side : kE32None;
+            } else {
+              ev = deg ? kE32Degenerate : lock ? kE32Lock : rule_left != left ? kE32Side : kE32None;
+            }
+            ev_s = s;
+          }
+        }
+      }
+    }
+
+    // ---- 4. the next candidate's records, loaded during the pass, into LDS
+    if (in_flight) {
+      const int mD = pf_meta & 0xFF, mn = (pf_meta >> 8) & 0xFF;
+      float4* Cn = Ct + (cpar ^ 1) * DMAX;
+      if (r < mD) Cn[r] = make_float4(pf_q0.S, pf_q0.Dm, pf_q0.Kc, __uint_as_float(pf_q0.slots));
+      if (r + kSeg32 < mD) Cn[r + kSeg32] = make_float4(pf_q1.S, pf_q1.Dm, pf_q1.Kc, __uint_as_float(pf_q1.slots));
+      if (r < mn) PN[r] = pf_w0;
+      if (r + kSeg32 < mn) PN[r + kSeg32] = pf_w1;
+      CFN[r] = pf_cf;
+      if (r == 0) {
+        MCN[0] = (int)pf_meta;
+        MCN[1] = pf_c;
+        MCN[2] = pf_p;
+      }
+      in_flight = false;
+      has_staged = true;
+    }
+
+    // ---- 5. the segment's first event, in step order
+    const uint64_t evb = __ballot(comp && r > 0 && ev != kE32None);
+    const uint32_t segm = (uint32_t)(evb >> seg0) & 0xFFFFu;
+    const int f = segm ? __ffs(segm) - 1 : kSeg32;
+    const int info = __shfl(ev | (ev_s << 8), seg0 + (f < kSeg32 ? f : 0));
+    int kind = f < kSeg32 ? (info & 0xFF) : kE32None;
+    int te = t0 - 1 + f;
+    if (cand >= 0 && force64) {  // links outside the solve order: to FP64 at t = 0
+      kind = kE32Band;
+      te = 0;
+    }
+    if (cand >= 0) {
+      bool done = false;
+      if (kind == kE32None) {
+        const int next = t0 + (kSeg32 - 1);
+        if (next >= T) {
+          if (r == 0) {
+            A.status[cand] = 0;
+            A.fail_step[cand] = -1;
+            if (A.esc_step) A.esc_step[cand] = -1;
+          }
+          done = true;
+        } else {
+          t0 = next;
+          ori_prov = ori;
+          fresh = false;
+          restarts = 0;
+        }
+      } else if (kind == kE32Side) {
+        if (f >= 2) {
+          ori_prov = ori;
+          fresh = false;
+          restarts = 0;
+        }
+        ori ^= 1u << (info >> 8);
+        t0 = te;
+        if (++restarts > D + 1) {
+          // cannot happen (each restart at one step moves the first change to a
+          // later dyad); the candidate is left without a final status
+          if (r == 0) A.status[cand] = kPending;
+          done = true;
+        }
+      } else if (kind == kE32Band) {
+        // to FP64 at step te from the positions of step te - 1 (lane f - 1), stored
+        // at the candidate's own dump row; at te = 0 the FP64 pass starts from the
+        // reference positions
+        if (te > 0 && r == f - 1) {
+          float2* dump = A.esc_pos + (size_t)item * J;
+          for (int sl = 0; sl < n; ++sl) dump[sl] = P[sl * bd + tid];
+        }
+        if (r == 0) {
+          if (A.esc_step) A.esc_step[cand] = (int16_t)te;
+          if (esc_pend) {
+            EscEntry e;
+            e.item = esc_item;
+            e.t = (int16_t)esc_te;
+            e.from_x0 = esc_te == 0 ? 1 : 0;
+            e.pad = 0;
+            A.esc[esc_i] = e;
+          }
+          esc_i = atomicAdd(&A.counters[kCntEsc], 1);  // read at the next hand-over or at the end
+          esc_pend = true;
+          esc_item = item;
+          esc_te = te;
+        }
+        done = true;
+      } else {
+        if (r == 0) {
+          A.status[cand] = (uint8_t)kind;
+          A.fail_step[cand] = (int16_t)te;
+          if (A.esc_step) A.esc_step[cand] = -1;
+        }
+        done = true;
+      }
+      if (done) cand = -1;
+    }
+  }
+}
+
+template <int DMAX, int MODE>
+void launch_par32_one(const SimArgs& a, const LaunchCfg& cfg, hipStream_t st) {
+  const int bd = cfg.waves * kWave;
+  hipLaunchKernelGGL((simpar32_kernel<DMAX, MODE>), dim3(cfg.grid), dim3(bd), par32_lds_bytes<DMAX>(a.nslot, bd, a.T),
+                     st, a);
+}
+
+template <int MODE>
+hipError_t dispatch_par32(const SimArgs& a, const LaunchCfg& cfg, hipStream_t st) {
+  if (a.T > kTableLds && (MODE & 2) == 0) return dispatch_par32<MODE | 2>(a, cfg, st);
+  switch (sim32_dmax(a.J)) {
+    case 5: launch_par32_one<5, MODE>(a, cfg, st); break;
+    case 11: launch_par32_one<11, MODE>(a, cfg, st); break;
+    case 18: launch_par32_one<18, MODE>(a, cfg, st); break;
+    default: launch_par32_one<30, MODE>(a, cfg, st); break;
+  }
+  return hipGetLastError();
+}
+
+template <int DMAX, int MODE>
+int occ_par32(int J, int waves, int T) {
+  int nb = 0;
+  const int lds = (int)par32_lds_bytes<DMAX>(J, waves * kWave, T);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, simpar32_kernel<DMAX, MODE>, waves * kWave, lds) !=
+      hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
+}
+
+template <int MODE>
+int occ_par32_d(int J, int waves, int T) {
+  switch (sim32_dmax(J)) {
+    case 5: return occ_par32<5, MODE>(J, waves, T);
+    case 11: return occ_par32<11, MODE>(J, waves, T);
+    case 18: return occ_par32<18, MODE>(J, waves, T);
+    default: return occ_par32<30, MODE>(J, waves, T);
+  }
+}
+
 }  // namespace
 
 int sim32_dmax(int J) {
@@ -448,6 +880,20 @@ int sim32_blocks_per_cu(int J, int mode, int T, int waves, int lds) {
     case 1: return occ_d<1>(d, waves, lds);
     case 2: return occ_d<2>(d, waves, lds);
     default: return occ_d<3>(d, waves, lds);
+  }
+}
+
+hipError_t launch_sim32_par(const SimArgs& a, int mode, const LaunchCfg& cfg, hipStream_t st) {
+  return mode == 0 ? dispatch_par32<0>(a, cfg, st) : dispatch_par32<1>(a, cfg, st);
+}
+
+int sim32_par_blocks_per_cu(int J, int mode, int T, int waves) {
+  const int m = (mode ? 1 : 0) | (T > kTableLds ? 2 : 0);
+  switch (m) {
+    case 0: return occ_par32_d<0>(J, waves, T);
+    case 1: return occ_par32_d<1>(J, waves, T);
+    case 2: return occ_par32_d<2>(J, waves, T);
+    default: return occ_par32_d<3>(J, waves, T);
   }
 }
 

@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
               }
             }
             const double2* x0 = reinterpret_cast<const double2*>(A.x0 + (size_t)c * J * 2);
-            const float2* dump = SRC == kFromEsc ? A.esc_pos + (size_t)p * J : nullptr;
+            const float2* dump = SRC == kFromEsc ? A.esc_pos + (size_t)(A.esc_by_item ? it : p) * J : nullptr;
             // initial positions, four slots at a time: the slot -> joint maps of
             // the group, then its positions, each set of loads issued together
             constexpr int NMAX = DMAX + 2;  // joints per candidate at most (J of this template)
@@ -490,13 +490,13 @@ __global__ void __launch_bounds__(256) simpar64_kernel(SimArgs A) {
   int cur_base = 0, cur_left = 0;
   bool no_more = false, exhausted = false;
   const int nwaves = gridDim.x * (bd / kWave);
+  const int items = A.counters[cnt_items];
   for (;;) {
     // ---- segments without a candidate take the next list entries, in lane order
     const uint64_t idle = __ballot(cand < 0 && r == 0);
     const int nidle = __popcll(idle);
     if (nidle == kWave / kSeg && exhausted) break;
     if (!exhausted && nidle > 0) {
-      const int items = A.counters[cnt_items];
       const int rank = __popcll(idle & ((1ull << seg0) - 1ull));  // idle segments before this one
       int p = -1, given = 0;
       for (int k = 0; k < 3 && given < nidle; ++k) {
@@ -519,6 +519,7 @@ __global__ void __launch_bounds__(256) simpar64_kernel(SimArgs A) {
       }
       exhausted = no_more && cur_left == 0;
       bool fill = false;  // this segment takes a candidate now
+      double2 v0s = make_double2(0.0, 0.0), v1s = make_double2(0.0, 0.0);
       if (p >= 0) {
         // list entry, then everything the item addresses, each level's loads issued
         // together; the segment's lanes share the per-entry and per-slot loads
@@ -552,7 +553,7 @@ __global__ void __launch_bounds__(256) simpar64_kernel(SimArgs A) {
         const double2* x0 = reinterpret_cast<const double2*>(A.x0 + (size_t)c * J * 2);
         double2 v0 = x0[j0], v1 = x0[j1];
         if (SRC == kFromEsc && !from_x0) {
-          const float2* dump = A.esc_pos + (size_t)p * J;
+          const float2* dump = A.esc_pos + (size_t)(A.esc_by_item ? it : p) * J;
           const float2 w0 = dump[min(s0, mn - 1)], w1 = dump[min(s1, mn - 1)];
           if (s0 <= mD) v0 = make_double2((double)w0.x, (double)w0.y);
           if (s1 <= mD) v1 = make_double2((double)w1.x, (double)w1.y);
@@ -589,17 +590,22 @@ __global__ void __launch_bounds__(256) simpar64_kernel(SimArgs A) {
             C[s1] = DyadC{q1.S, q1.Dm, EXACT ? q1.ra2 : 0.5 * (q1.ra2 - q1.rb2), q1.rb2};
             SL[s1] = l1;
           }
-          // starting positions into every lane of the segment
-          for (int k = 0; k < kSeg; ++k) {
-            if (s0 < n) P[s0 * bd + tid - r + k] = v0;
-            if (s1 < n) P[s1 * bd + tid - r + k] = v1;
-          }
+          v0s = v0;
+          v1s = v1;
         }
       }
-      // the segment's LDS writes are complete before any lane reads them
-      __builtin_amdgcn_s_waitcnt(0xC07F);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // starting positions of slots k and k + 16, broadcast from lane k of the
+      // segment; every lane writes its own column (conflict-free)
+      for (int k = 0; k < kSeg; ++k) {
+        const double2 u0 = make_double2(__shfl(v0s.x, seg0 + k), __shfl(v0s.y, seg0 + k));
+        const double2 u1 = make_double2(__shfl(v1s.x, seg0 + k), __shfl(v1s.y, seg0 + k));
+        if (fill && k < n) P[k * bd + tid] = u0;
+        if (fill && k + kSeg < n) P[(k + kSeg) * bd + tid] = u1;
+      }
+      // the segment's LDS writes are complete before any lane reads them (LDS
+      // operations of a wave complete in order; only the compiler is held back)
+      __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+      asm volatile("" ::: "memory");
       // first guess of the sides: those of the starting positions (lane r: dyads r, r + 16)
       bool g0 = false, g1 = false;
       if (fill) {

@@ -128,6 +128,27 @@ def test_parallel_in_time_fp64_passes(ctx, L):
     assert np.array_equal(z["path"], ref["path"], equal_nan=True)
 
 
+@pytest.mark.parametrize("precision", [0, 2])
+def test_parallel_in_time_fp32_pass(ctx, L, precision):
+    """The FP32 pass computed parallel in time takes every decision of the
+    step-by-step pass: statuses, failure and hand-over steps and paths equal."""
+    _say(f"[par32] precision={precision}")
+    b = gen.workload("dyad_6_20", 30000, seed=22)
+    db = L.to_device(b)
+    res = {}
+    try:
+        for mode in (0, 1):
+            ctx.set_option("par32", mode)
+            res[mode] = _np(ctx.simulate(db, T=200, precision=precision, write=L.WRITE_ALL, path_dtype=L.F64))
+    finally:
+        ctx.set_option("par32", 1)
+    a, z = res[0], res[1]
+    for k in ("status", "fail_step", "esc_step"):
+        diff = np.nonzero(a[k] != z[k])[0]
+        assert diff.size == 0, (k, diff[:10], a[k][diff[:10]], z[k][diff[:10]])
+    assert np.array_equal(a["path"], z["path"], equal_nan=True)
+
+
 @pytest.mark.parametrize("J", [7, 10, 13, 20, 22, 32])
 def test_malformed_candidates(ctx, L, J):
     """Every way of breaking the input contract, mixed into valid batches of each
