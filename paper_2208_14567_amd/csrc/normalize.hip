@@ -1,5 +1,6 @@
-// normalize.hip -- path normalisation, one wave (64 lanes) per path; FP32 paths in
-// and out, moments and rotations evaluated in FP64.
+// normalize.hip -- path normalisation; FP32 paths in and out, moments and
+// rotations evaluated in FP64.  PCA mode: four paths per wave (16 lanes each);
+// DIAMETER mode: one wave per path.
 //
 // DIAMETER mode is the paper's rule (Methodology, "Dataset Curation &
 // Processing"): find the longest chord of the path, turn it onto +x, scale it to
@@ -206,11 +207,126 @@ __global__ void __launch_bounds__(kNormWaves * kWave) normalize_kernel(const flo
   }
 }
 
+// PCA mode, a 16-lane group per path (four paths per wave): mean, then the
+// second moments about it in one pass, the third moment along the principal axis,
+// and the output; every division by the RMS radius is a multiplication by its
+// reciprocal.
+constexpr int kPcaLanes = 16;
+
+__device__ __forceinline__ double gsumd(double v) {
+#pragma unroll
+  for (int o = kPcaLanes / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__global__ void __launch_bounds__(kNormWaves * kWave) pca_kernel(const float* paths, int32_t P, const int32_t* count,
+                                                                int32_t T, float* out, float* xform) {
+  if (count) P = min(P, *count);
+  extern __shared__ float2 pts_all[];  // [kNormWaves * 4][T]
+  const int g = threadIdx.x / kPcaLanes;  // group of the workgroup
+  const int l = threadIdx.x & (kPcaLanes - 1);
+  float2* pts = pts_all + (size_t)g * T;
+  const int groups_total = gridDim.x * (blockDim.x / kPcaLanes);
+  // every group of a wave runs the same number of iterations (uniform shuffles)
+  const int iters = (P + groups_total - 1) / groups_total;
+  for (int k = 0; k < iters; ++k) {
+    const int p = (k * gridDim.x + blockIdx.x) * (blockDim.x / kPcaLanes) + g;
+    const bool live = p < P;
+    const float2* src = reinterpret_cast<const float2*>(paths) + (size_t)(live ? p : 0) * T;
+    float2* dst = reinterpret_cast<float2*>(out) + (size_t)p * T;
+    const float2 p0 = src[0];
+    for (int i = l; i < T; i += kPcaLanes) pts[i] = src[i];
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the group's LDS writes before its reads
+    asm volatile("" ::: "memory");
+    const double ox = p0.x, oy = p0.y;
+    double sx = 0.0, sy = 0.0;
+    for (int i = l; i < T; i += kPcaLanes) {
+      sx += (double)pts[i].x - ox;
+      sy += (double)pts[i].y - oy;
+    }
+    const double mx = gsumd(sx) / T, my = gsumd(sy) / T;
+    double axx = 0.0, axy = 0.0, ayy = 0.0;
+    for (int i = l; i < T; i += kPcaLanes) {
+      const double qx = ((double)pts[i].x - ox) - mx, qy = ((double)pts[i].y - oy) - my;
+      axx += qx * qx;
+      axy += qx * qy;
+      ayy += qy * qy;
+    }
+    axx = gsumd(axx);
+    axy = gsumd(axy);
+    ayy = gsumd(ayy);
+    const double s = sqrt((axx + ayy) / T);
+    const double cx = ox + mx, cy = oy + my;
+    float xf[5];
+    if (!(s >= 1e-12)) {
+      if (live)
+        for (int i = l; i < T; i += kPcaLanes) dst[i] = make_float2(0.f, 0.f);
+      xf[0] = (float)cx;
+      xf[1] = (float)cy;
+      xf[2] = 0.f;
+      xf[3] = 0.f;
+      xf[4] = 1.f;
+    } else {
+      const double is = 1.0 / s;
+      const double norm = is * is / T;  // covariance of the scaled path
+      const double cxx = axx * norm, cxy = axy * norm, cyy = ayy * norm;
+      const double dxy = cxx - cyy;
+      const double gap = sqrt(dxy * dxy + 4.0 * cxy * cxy);
+      int flags = 0;
+      double phi = 0.5 * atan2(2.0 * cxy, dxy);
+      if (gap < 1e-4 * (cxx + cyy)) {
+        phi = 0.0;
+        flags |= 2;
+      }
+      const double c = cos(phi), sn = sin(phi);
+      double m3 = 0.0;
+      for (int i = l; i < T; i += kPcaLanes) {
+        const double qx = (((double)pts[i].x - ox) - mx) * is, qy = (((double)pts[i].y - oy) - my) * is;
+        const double rx = c * qx + sn * qy;
+        m3 += rx * rx * rx;
+      }
+      m3 = gsumd(m3);
+      double sign = 1.0;
+      if (fabs(m3) < 1e-6 * T) {
+        flags |= 4;
+      } else if (m3 < 0.0) {
+        sign = -1.0;
+        phi += 3.14159265358979323846;
+      }
+      const double a = sign * c, b = sign * sn;
+      if (live)
+        for (int i = l; i < T; i += kPcaLanes) {
+          const double qx = (((double)pts[i].x - ox) - mx) * is, qy = (((double)pts[i].y - oy) - my) * is;
+          dst[i] = make_float2((float)(a * qx + b * qy), (float)(-b * qx + a * qy));
+        }
+      xf[0] = (float)cx;
+      xf[1] = (float)cy;
+      xf[2] = (float)s;
+      xf[3] = (float)phi;
+      xf[4] = (float)flags;
+    }
+    if (live && l < 5) {
+      const float v = l == 0 ? xf[0] : l == 1 ? xf[1] : l == 2 ? xf[2] : l == 3 ? xf[3] : xf[4];
+      xform[(size_t)p * 5 + l] = v;
+    }
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // this path's reads before the next path's writes
+    asm volatile("" ::: "memory");
+  }
+}
+
 }  // namespace
 
 hipError_t launch_normalize(const float* paths, int32_t P, const int32_t* count, int32_t T, int32_t mode,
                             float* out, float* xform, hipStream_t st) {
   if (P <= 0) return hipSuccess;
+  if (mode == 0 && T <= 512) {  // 16 paths of T points in a workgroup's LDS (64 KiB at most)
+    const int per_block = kNormWaves * kWave / kPcaLanes;
+    int blocks = (P + per_block - 1) / per_block;
+    if (blocks > 4096) blocks = 4096;
+    const size_t lds = (size_t)per_block * T * sizeof(float2);
+    hipLaunchKernelGGL(pca_kernel, dim3(blocks), dim3(kNormWaves * kWave), lds, st, paths, P, count, T, out, xform);
+    return hipGetLastError();
+  }
   int blocks = (P + kNormWaves - 1) / kNormWaves;
   if (blocks > 4096) blocks = 4096;
   size_t lds = (size_t)kNormWaves * T * sizeof(float2);

@@ -361,6 +361,22 @@ def test_normalize_closed_forms(ctx, L):
     assert np.allclose(o[1, 0], [0, 0.5], atol=1e-6) and np.allclose(o[1, -1], [1, 0.5], atol=1e-6)
 
 
+@pytest.mark.parametrize("T,P", [(7, 37), (200, 1001), (512, 50), (513, 50), (3000, 9)])
+def test_normalize_pca_lengths(ctx, L, T, P):
+    """PCA normalisation of random-walk paths of several lengths (the grouped
+    kernel up to 512 points, one wave per path above) against the oracle."""
+    rng = np.random.default_rng(T)
+    steps = rng.normal(size=(P, T, 2)) * rng.uniform(0.01, 1.0, size=(P, 1, 2))
+    paths = (np.cumsum(steps, axis=1) + rng.uniform(-5, 5, size=(P, 1, 2))).astype(np.float32)
+    out, xf = ctx.normalize_paths(torch.from_numpy(paths).cuda(), L.NORM_PCA)
+    out, xf = out.cpu().numpy(), xf.cpu().numpy()
+    ro, rxf = oracle.normalize_paths(paths.astype(np.float64), L.NORM_PCA)
+    plain = (rxf[:, 4] == 0) & (xf[:, 4] == 0)
+    assert plain.mean() > 0.9
+    assert np.abs(out[plain] - ro[plain]).max() <= 1e-5
+    assert np.allclose(xf[plain, :3], rxf[plain, :3], rtol=1e-5, atol=1e-6)
+
+
 def test_bad_arguments_raise(ctx, L):
     b = L.to_device(gen.workload("fourbar", 4))
     with pytest.raises(L.LinksError):
