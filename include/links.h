@@ -206,6 +206,8 @@ int links_set_tuning(links_ctx* ctx, int waves32, int refill_min, int waves64);
  *                     restarted where the rule changes side (results identical to
  *                     the step-by-step pass).  0: none; 1 (default): the hand-over
  *                     pass (whose long FP64 runs are few); 2: every FP64 pass;
+ *   "seg64"           lanes per candidate of the parallel hand-over pass: 4, 8
+ *                     (default) or 16 (the other parallel passes use 16);
  *   "par32"           1: the FP32 pass runs parallel in time the same way (same
  *                     decisions and hand-over steps as the step-by-step pass);
  *                     0 (default).  Ignored when "deesc" > 0. */

@@ -72,6 +72,7 @@ struct links_ctx {
   // 0 none, 1 the hand-over pass, 2 every FP64 pass.  The return to FP32 after a
   // hand-over (deesc > 0) keeps the step-by-step pass.
   int par64 = 1;
+  int seg64 = 8;  // lanes per candidate of the parallel hand-over pass
   // the FP32 pass computed parallel in time (with deesc > 0 the step-by-step pass);
   // off by default: its larger LDS footprint per wave costs more than the idle
   // lanes it saves on the measured workloads
@@ -290,6 +291,11 @@ int links_set_option(links_ctx* ctx, const char* name, int value) {
     ctx->par32 = value != 0;
     return LINKS_OK;
   }
+  if (k == "seg64") {
+    if (value != 4 && value != 8 && value != 16) return fail(LINKS_ERR_ARG, "seg64 must be 4, 8 or 16");
+    ctx->seg64 = value;
+    return LINKS_OK;
+  }
   if (k == "par64") {
     if (value < 0 || value > 2) return fail(LINKS_ERR_ARG, "par64 must be 0, 1 or 2");
     ctx->par64 = value;
@@ -310,6 +316,7 @@ int links_get_option(links_ctx* ctx, const char* name, int* value) {
   else if (k == "deesc") *value = ctx->deesc;
   else if (k == "exact_handover") *value = ctx->exact_handover ? 1 : 0;
   else if (k == "par64") *value = ctx->par64;
+  else if (k == "seg64") *value = ctx->seg64;
   else if (k == "par32") *value = ctx->par32 ? 1 : 0;
   else return fail(LINKS_ERR_ARG, "unknown option '%s'", name);
   return LINKS_OK;
@@ -559,7 +566,6 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   sa.res = res;
   sa.res_pos = res_pos;
   sa.deesc = 0;
-  sa.esc_by_item = 0;
   sa.resume = 0;
   sa.chunk = ctx->chunk;
 
@@ -574,7 +580,8 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   // an FP64 pass, step by step or parallel in time
   auto run64 = [&](const SimArgs& a, int source, bool exact, LaunchCfg cfg, bool par) -> hipError_t {
     if (par) {
-      cfg.grid = grid_for(ctx, "par64", sim64_par_blocks_per_cu(J, source, exact, cfg.waves));
+      cfg.seg = source == kFromEsc ? ctx->seg64 : 16;
+      cfg.grid = grid_for(ctx, "par64", sim64_par_blocks_per_cu(J, source, exact, cfg.waves, cfg.seg));
       return launch_sim64_par(a, source, exact, cfg, st);
     }
     cfg.grid = grid_for(ctx, "sim64", sim64_blocks_per_cu(J, source, exact, cfg.waves, lds64));
@@ -604,8 +611,8 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
     if ((rc = mark(ctx, 3, st))) return rc;
     SimArgs h1 = sa64;
     h1.deesc = ctx->deesc;
-    h1.esc_by_item = ctx->par32 && ctx->deesc == 0 ? 1 : 0;  // the parallel FP32 pass dumps by item
-    HIP_CHECK(run64(h1, kFromEsc, ctx->exact_handover, c64, ctx->par64 >= 1 && ctx->deesc == 0));
+    const bool par_h = ctx->par64 >= 1 && ctx->deesc == 0;
+    HIP_CHECK(run64(h1, kFromEsc, ctx->exact_handover, c64, par_h));
     if (ctx->deesc > 0) {
       // the returned candidates continue in FP32 (their own counters and
       // hand-over queue), and what they hand over again is finished in FP64

@@ -98,8 +98,7 @@ struct SimArgs {
   int32_t* path_list;  // [B] sorted positions of the candidates whose path is written
   int32_t* path_row;   // [B] output row of each valid candidate (WRITE_VALID), -1 beyond cap
   int32_t write_all;   // every simulated candidate's path is output (row = candidate)
-  float2* esc_pos;  // [B][J] FP32 slot positions at hand-over
-  int32_t esc_by_item;  // dumps at the candidate's sorted position (else at the queue entry)
+  float2* esc_pos;  // [B][J] FP32 slot positions at hand-over, row = the candidate's sorted position
   // crank table
   const float2* cs32;   // [T] (cos, sin) rounded from FP64
   const double2* cs64;  // [T]

@@ -110,6 +110,7 @@ struct LaunchCfg {
   int grid;
   int waves;
   int refill_min;
+  int seg = 16;  // lanes per candidate of a parallel-in-time pass (4, 8 or 16)
 };
 // FP32 pass: mode 0 escalates to FP64, mode 1 never escalates.
 hipError_t launch_sim32(const SimArgs& a, int mode, const LaunchCfg& cfg, hipStream_t st);
@@ -132,7 +133,7 @@ int sim32_blocks_per_cu(int J, int mode, int T, int waves, int lds_bytes);
 int sim64_blocks_per_cu(int J, int source, bool exact, int waves, int lds_bytes);
 // the same passes computed parallel in time (16-lane segments per candidate)
 hipError_t launch_sim64_par(const SimArgs& a, int source, bool exact, const LaunchCfg& cfg, hipStream_t st);
-int sim64_par_blocks_per_cu(int J, int source, bool exact, int waves);
+int sim64_par_blocks_per_cu(int J, int source, bool exact, int waves, int seg);
 
 // Path normalisation, one wave per path.
 hipError_t launch_normalize(const float* paths, int32_t P, const int32_t* count, int32_t T, int32_t mode,

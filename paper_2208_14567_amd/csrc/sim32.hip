@@ -367,7 +367,7 @@ sim32_kernel(SimArgs A) {
         e.from_x0 = force64 ? 1 : 0;
         e.pad = 0;
         A.esc[i] = e;
-        float2* dump = A.esc_pos + (size_t)i * J;
+        float2* dump = A.esc_pos + (size_t)item * J;  // the candidate's own row
         for (int sl = 0; sl < n; ++sl) dump[sl] = P[sl * bd + tid];
         if (A.esc_step && !A.resume) A.esc_step[cand] = (int16_t)t;  // the first hand-over
       }
@@ -769,8 +769,8 @@ __global__ void __launch_bounds__(256) simpar32_kernel(SimArgs A) {
         }
       } else if (kind == kE32Band) {
         // to FP64 at step te from the positions of step te - 1 (lane f - 1), stored
-        // at the candidate's own dump row; at te = 0 the FP64 pass starts from the
-        // reference positions
+        // at the candidate's own dump row (as every hand-over dump is); at te = 0 the
+        // FP64 pass starts from the reference positions
         if (te > 0 && r == f - 1) {
           float2* dump = A.esc_pos + (size_t)item * J;
           for (int sl = 0; sl < n; ++sl) dump[sl] = P[sl * bd + tid];

@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
               }
             }
             const double2* x0 = reinterpret_cast<const double2*>(A.x0 + (size_t)c * J * 2);
-            const float2* dump = SRC == kFromEsc ? A.esc_pos + (size_t)(A.esc_by_item ? it : p) * J : nullptr;
+            const float2* dump = SRC == kFromEsc ? A.esc_pos + (size_t)it * J : nullptr;
             // initial positions, four slots at a time: the slot -> joint maps of
             // the group, then its positions, each set of loads issued together
             constexpr int NMAX = DMAX + 2;  // joints per candidate at most (J of this template)
@@ -419,7 +419,7 @@ int occ_for(int J, int waves, int lds) {
 
 // ---- the same passes, parallel in time.
 //
-// A segment of kSeg = 16 lanes (one DPP row) holds one candidate, and lane r of the
+// A segment of W lanes (within one 16-lane DPP row) holds one candidate, and lane r of the
 // segment computes step t0 - 1 + r.  Lane 0, the provider, recomputes the last step
 // already decided (or holds the starting positions), so that every other lane finds
 // its candidate's previous positions in its left neighbour.  Every dyad is placed on
@@ -433,7 +433,6 @@ int occ_for(int J, int waves, int lds) {
 // outcome at that step; a side change flips the dyad's bit and the segment
 // restarts at that step, where the rule now agrees with the bit up to that dyad (so
 // at most D restarts happen at one step).
-constexpr int kSeg = 16;
 
 // the value held by lane - 1 of the same 16-lane row (lane 0 of a row gets 0)
 __device__ __forceinline__ double row_prev(double v) {
@@ -452,13 +451,16 @@ struct DyadC {
 
 // LDS of the parallel pass: positions [nslot][bd] and, per segment, DMAX entries
 // of constants and their parent slots
-template <int DMAX>
+template <int DMAX, int W>
 __host__ __device__ constexpr size_t par_lds_bytes(int nslot, int bd) {
-  return (size_t)nslot * bd * sizeof(double2) + (size_t)(bd / kSeg) * DMAX * (sizeof(DyadC) + sizeof(uint32_t));
+  return (size_t)nslot * bd * sizeof(double2) + (size_t)(bd / W) * DMAX * (sizeof(DyadC) + sizeof(uint32_t));
 }
 
-template <int DMAX, int SRC, bool EXACT>
+template <int DMAX, int SRC, bool EXACT, int W>
 __global__ void __launch_bounds__(256) simpar64_kernel(SimArgs A) {
+  static_assert(W == 4 || W == 8 || W == 16, "segments lie within 16-lane DPP rows");
+  constexpr int NQ = 32 / W;  // entries and slots each lane loads at a refill
+  constexpr uint32_t WMASK = (1u << W) - 1u;
   extern __shared__ unsigned char smem[];
   const int bd = blockDim.x;
   const int tid = threadIdx.x;
@@ -467,12 +469,12 @@ __global__ void __launch_bounds__(256) simpar64_kernel(SimArgs A) {
   const int J = A.J;
   const int Bs = A.Bs;
   const int lane = __lane_id();
-  const int r = lane & (kSeg - 1);    // position in the segment; 0 is the provider
-  const int seg0 = lane & ~(kSeg - 1);
-  const int segb = tid / kSeg;        // segment of the workgroup
+  const int r = lane & (W - 1);    // position in the segment; 0 is the provider
+  const int seg0 = lane & ~(W - 1);
+  const int segb = tid / W;        // segment of the workgroup
   DyadC* C = reinterpret_cast<DyadC*>(smem + (size_t)A.nslot * bd * sizeof(double2)) + segb * DMAX;
   uint32_t* SL = reinterpret_cast<uint32_t*>(smem + (size_t)A.nslot * bd * sizeof(double2) +
-                                             (size_t)(bd / kSeg) * DMAX * sizeof(DyadC)) + segb * DMAX;
+                                             (size_t)(bd / W) * DMAX * sizeof(DyadC)) + segb * DMAX;
   const int cnt_next = SRC == kFromEsc ? kCntEscNext : SRC == kFromPath ? kCntPathNext : kCntNext;
   const int cnt_items = SRC == kFromEsc ? kCntEsc : SRC == kFromPath ? kCntPath : kCntItems;
 
@@ -495,7 +497,7 @@ __global__ void __launch_bounds__(256) simpar64_kernel(SimArgs A) {
     // ---- segments without a candidate take the next list entries, in lane order
     const uint64_t idle = __ballot(cand < 0 && r == 0);
     const int nidle = __popcll(idle);
-    if (nidle == kWave / kSeg && exhausted) break;
+    if (nidle == kWave / W && exhausted) break;
     if (!exhausted && nidle > 0) {
       const int rank = __popcll(idle & ((1ull << seg0) - 1ull));  // idle segments before this one
       int p = -1, given = 0;
@@ -519,7 +521,9 @@ __global__ void __launch_bounds__(256) simpar64_kernel(SimArgs A) {
       }
       exhausted = no_more && cur_left == 0;
       bool fill = false;  // this segment takes a candidate now
-      double2 v0s = make_double2(0.0, 0.0), v1s = make_double2(0.0, 0.0);
+      double2 vs[NQ];
+#pragma unroll
+      for (int k = 0; k < NQ; ++k) vs[k] = make_double2(0.0, 0.0);
       if (p >= 0) {
         // list entry, then everything the item addresses, each level's loads issued
         // together; the segment's lanes share the per-entry and per-slot loads
@@ -541,22 +545,28 @@ __global__ void __launch_bounds__(256) simpar64_kernel(SimArgs A) {
         int fs = -1;
         if (SRC == kFromPath) fs = A.fail_step[c];
         const int mD = m.D, mn = m.n;
-        // lane r: entries r and r + 16, slots r and r + 16
-        const int s0 = r, s1 = r + kSeg;
-        const int e0 = min(s0, max(mD - 1, 0)), e1 = min(s1, max(mD - 1, 0));
-        const DyadF64 q0 = A.dd[(size_t)e0 * Bs + it];
-        const DyadF64 q1 = A.dd[(size_t)e1 * Bs + it];
-        const uint32_t l0 = A.df[(size_t)e0 * Bs + it].slots;
-        const uint32_t l1 = A.df[(size_t)e1 * Bs + it].slots;
-        const int j0 = A.slot_joint[(size_t)min(s0, mn - 1) * Bs + it];
-        const int j1 = A.slot_joint[(size_t)min(s1, mn - 1) * Bs + it];
+        // lane r: entries and slots r + k W
+        DyadF64 q[NQ];
+        uint32_t lq[NQ];
+        int jq[NQ];
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+          const int e = min(r + k * W, max(mD - 1, 0));
+          q[k] = A.dd[(size_t)e * Bs + it];
+          lq[k] = A.df[(size_t)e * Bs + it].slots;
+          jq[k] = A.slot_joint[(size_t)min(r + k * W, mn - 1) * Bs + it];
+        }
         const double2* x0 = reinterpret_cast<const double2*>(A.x0 + (size_t)c * J * 2);
-        double2 v0 = x0[j0], v1 = x0[j1];
+        double2 vq[NQ];
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) vq[k] = x0[jq[k]];
         if (SRC == kFromEsc && !from_x0) {
-          const float2* dump = A.esc_pos + (size_t)(A.esc_by_item ? it : p) * J;
-          const float2 w0 = dump[min(s0, mn - 1)], w1 = dump[min(s1, mn - 1)];
-          if (s0 <= mD) v0 = make_double2((double)w0.x, (double)w0.y);
-          if (s1 <= mD) v1 = make_double2((double)w1.x, (double)w1.y);
+          const float2* dump = A.esc_pos + (size_t)it * J;
+#pragma unroll
+          for (int k = 0; k < NQ; ++k) {
+            const float2 w = dump[min(r + k * W, mn - 1)];
+            if (r + k * W <= mD) vq[k] = make_double2((double)w.x, (double)w.y);
+          }
         }
         item = it;
         t_end = T;
@@ -582,48 +592,45 @@ __global__ void __launch_bounds__(256) simpar64_kernel(SimArgs A) {
           fresh = true;
           restarts = 0;
           fill = true;
-          if (s0 < D) {
-            C[s0] = DyadC{q0.S, q0.Dm, EXACT ? q0.ra2 : 0.5 * (q0.ra2 - q0.rb2), q0.rb2};
-            SL[s0] = l0;
+#pragma unroll
+          for (int k = 0; k < NQ; ++k) {
+            const int se = r + k * W;
+            if (se < D) {
+              C[se] = DyadC{q[k].S, q[k].Dm, EXACT ? q[k].ra2 : 0.5 * (q[k].ra2 - q[k].rb2), q[k].rb2};
+              SL[se] = lq[k];
+            }
+            vs[k] = vq[k];
           }
-          if (s1 < D) {
-            C[s1] = DyadC{q1.S, q1.Dm, EXACT ? q1.ra2 : 0.5 * (q1.ra2 - q1.rb2), q1.rb2};
-            SL[s1] = l1;
-          }
-          v0s = v0;
-          v1s = v1;
         }
       }
-      // starting positions of slots k and k + 16, broadcast from lane k of the
+      // starting positions of slots kk + k W, broadcast from lane kk of the
       // segment; every lane writes its own column (conflict-free)
-      for (int k = 0; k < kSeg; ++k) {
-        const double2 u0 = make_double2(__shfl(v0s.x, seg0 + k), __shfl(v0s.y, seg0 + k));
-        const double2 u1 = make_double2(__shfl(v1s.x, seg0 + k), __shfl(v1s.y, seg0 + k));
-        if (fill && k < n) P[k * bd + tid] = u0;
-        if (fill && k + kSeg < n) P[(k + kSeg) * bd + tid] = u1;
+      for (int kk = 0; kk < W; ++kk) {
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+          const double2 u = make_double2(__shfl(vs[k].x, seg0 + kk), __shfl(vs[k].y, seg0 + kk));
+          if (fill && kk + k * W < n) P[(kk + k * W) * bd + tid] = u;
+        }
       }
       // the segment's LDS writes are complete before any lane reads them (LDS
       // operations of a wave complete in order; only the compiler is held back)
       __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
       asm volatile("" ::: "memory");
-      // first guess of the sides: those of the starting positions (lane r: dyads r, r + 16)
-      bool g0 = false, g1 = false;
-      if (fill) {
-        if (r < D) {
-          const uint32_t sl = SL[r];
-          const double2 pa = P[(sl & 0xFF) * bd + tid], pb = P[((sl >> 8) & 0xFF) * bd + tid], pk = P[r * bd + tid];
-          g0 = (pb.x - pa.x) * (pk.y - pa.y) - (pb.y - pa.y) * (pk.x - pa.x) >= 0.0;
+      // first guess of the sides: those of the starting positions (lane r: dyads r + k W)
+      uint32_t og = 0u;
+#pragma unroll
+      for (int k = 0; k < NQ; ++k) {
+        const int se = r + k * W;
+        bool g = false;
+        if (fill && se < D) {
+          const uint32_t sl = SL[se];
+          const double2 pa = P[(sl & 0xFF) * bd + tid], pb = P[((sl >> 8) & 0xFF) * bd + tid], pk = P[se * bd + tid];
+          g = (pb.x - pa.x) * (pk.y - pa.y) - (pb.y - pa.y) * (pk.x - pa.x) >= 0.0;
         }
-        if (r + kSeg < D) {
-          const uint32_t sl = SL[r + kSeg];
-          const double2 pa = P[(sl & 0xFF) * bd + tid], pb = P[((sl >> 8) & 0xFF) * bd + tid];
-          const double2 pk = P[(r + kSeg) * bd + tid];
-          g1 = (pb.x - pa.x) * (pk.y - pa.y) - (pb.y - pa.y) * (pk.x - pa.x) >= 0.0;
-        }
+        og |= (uint32_t)((__ballot(g) >> seg0) & WMASK) << (k * W);
       }
-      const uint64_t b0 = __ballot(g0), b1 = __ballot(g1);
       if (fill) {
-        ori = (uint32_t)((b0 >> seg0) & 0xFFFFu) | ((uint32_t)((b1 >> seg0) & 0xFFFFu) << kSeg);
+        ori = og;
         ori_prov = ori;
       }
       // largest solve order among the wave's segments (bounds the dyad loop)
@@ -736,10 +743,10 @@ __global__ void __launch_bounds__(256) simpar64_kernel(SimArgs A) {
 
     // ---- the segment's first event, in step order
     const uint64_t evb = __ballot(comp && r > 0 && ev != kEvNone);
-    const uint32_t segm = (uint32_t)(evb >> seg0) & 0xFFFFu;
-    const int f = segm ? __ffs(segm) - 1 : kSeg;
-    const int info = __shfl(ev | (ev_s << 8), seg0 + (f < kSeg ? f : 0));
-    const int kind = f < kSeg ? (info & 0xFF) : kEvNone;
+    const uint32_t segm = (uint32_t)(evb >> seg0) & WMASK;
+    const int f = segm ? __ffs(segm) - 1 : W;
+    const int info = __shfl(ev | (ev_s << 8), seg0 + (f < W ? f : 0));
+    const int kind = f < W ? (info & 0xFF) : kEvNone;
     if (SRC == kFromPath && comp && r > 0 && r < f) {
       const double2 po = P[out_slot * bd + tid];
       if (A.path_f64)
@@ -751,7 +758,7 @@ __global__ void __launch_bounds__(256) simpar64_kernel(SimArgs A) {
       bool done = false;
       const int te = t0 - 1 + f;  // step of the event
       if (kind == kEvNone) {
-        const int next = t0 + (kSeg - 1);
+        const int next = t0 + (W - 1);
         if (next >= t_end) {
           if (SRC != kFromPath && r == 0) {
             A.status[cand] = 0;
@@ -785,7 +792,7 @@ __global__ void __launch_bounds__(256) simpar64_kernel(SimArgs A) {
           // a failure here (possible only within rounding of a threshold) leaves the
           // rest of the row NaN
           const double nan = __builtin_nan("");
-          for (int tt = te + r; tt < t_end; tt += kSeg) {
+          for (int tt = te + r; tt < t_end; tt += W) {
             if (A.path_f64)
               reinterpret_cast<double2*>(A.path)[row * T + tt] = make_double2(nan, nan);
             else
@@ -803,11 +810,20 @@ __global__ void __launch_bounds__(256) simpar64_kernel(SimArgs A) {
   }
 }
 
+template <int DMAX, int SRC, bool EXACT, int W>
+void launch_par_w(const SimArgs& a, const LaunchCfg& cfg, hipStream_t st) {
+  const int bd = cfg.waves * kWave;
+  const size_t lds = par_lds_bytes<DMAX, W>(a.nslot, bd);
+  hipLaunchKernelGGL((simpar64_kernel<DMAX, SRC, EXACT, W>), dim3(cfg.grid), dim3(bd), lds, st, a);
+}
+
 template <int DMAX, int SRC, bool EXACT>
 void launch_par_one(const SimArgs& a, const LaunchCfg& cfg, hipStream_t st) {
-  const int bd = cfg.waves * kWave;
-  const size_t lds = par_lds_bytes<DMAX>(a.nslot, bd);
-  hipLaunchKernelGGL((simpar64_kernel<DMAX, SRC, EXACT>), dim3(cfg.grid), dim3(bd), lds, st, a);
+  if constexpr (SRC == kFromEsc) {
+    if (cfg.seg == 8) return launch_par_w<DMAX, SRC, EXACT, 8>(a, cfg, st);
+    if (cfg.seg == 4) return launch_par_w<DMAX, SRC, EXACT, 4>(a, cfg, st);
+  }
+  launch_par_w<DMAX, SRC, EXACT, 16>(a, cfg, st);
 }
 
 template <int SRC, bool EXACT>
@@ -821,23 +837,32 @@ hipError_t dispatch_par(const SimArgs& a, const LaunchCfg& cfg, hipStream_t st) 
   return hipGetLastError();
 }
 
-template <int DMAX, int SRC, bool EXACT>
-int occ_par(int J, int waves) {
-  const int lds = (int)par_lds_bytes<DMAX>(J, waves * kWave);
+template <int DMAX, int SRC, bool EXACT, int W>
+int occ_par_w(int J, int waves) {
+  const int lds = (int)par_lds_bytes<DMAX, W>(J, waves * kWave);
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, simpar64_kernel<DMAX, SRC, EXACT>, waves * kWave, lds) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, simpar64_kernel<DMAX, SRC, EXACT, W>, waves * kWave, lds) !=
       hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
 }
 
+template <int DMAX, int SRC, bool EXACT>
+int occ_par(int J, int waves, int seg) {
+  if constexpr (SRC == kFromEsc) {
+    if (seg == 8) return occ_par_w<DMAX, SRC, EXACT, 8>(J, waves);
+    if (seg == 4) return occ_par_w<DMAX, SRC, EXACT, 4>(J, waves);
+  }
+  return occ_par_w<DMAX, SRC, EXACT, 16>(J, waves);
+}
+
 template <int SRC, bool EXACT>
-int occ_par_for(int J, int waves) {
+int occ_par_for(int J, int waves, int seg) {
   switch (sim32_dmax(J)) {
-    case 5: return occ_par<5, SRC, EXACT>(J, waves);
-    case 11: return occ_par<11, SRC, EXACT>(J, waves);
-    case 18: return occ_par<18, SRC, EXACT>(J, waves);
-    default: return occ_par<30, SRC, EXACT>(J, waves);
+    case 5: return occ_par<5, SRC, EXACT>(J, waves, seg);
+    case 11: return occ_par<11, SRC, EXACT>(J, waves, seg);
+    case 18: return occ_par<18, SRC, EXACT>(J, waves, seg);
+    default: return occ_par<30, SRC, EXACT>(J, waves, seg);
   }
 }
 
@@ -890,18 +915,18 @@ hipError_t launch_sim64_par(const SimArgs& a, int source, bool exact, const Laun
   }
 }
 
-int sim64_par_blocks_per_cu(int J, int source, bool exact, int waves) {
+int sim64_par_blocks_per_cu(int J, int source, bool exact, int waves, int seg) {
   if (exact) {
     switch (source) {
-      case kFromEsc: return occ_par_for<kFromEsc, true>(J, waves);
-      case kFromPath: return occ_par_for<kFromPath, true>(J, waves);
-      default: return occ_par_for<kFromPerm, true>(J, waves);
+      case kFromEsc: return occ_par_for<kFromEsc, true>(J, waves, seg);
+      case kFromPath: return occ_par_for<kFromPath, true>(J, waves, seg);
+      default: return occ_par_for<kFromPerm, true>(J, waves, seg);
     }
   }
   switch (source) {
-    case kFromEsc: return occ_par_for<kFromEsc, false>(J, waves);
-    case kFromPath: return occ_par_for<kFromPath, false>(J, waves);
-    default: return occ_par_for<kFromPerm, false>(J, waves);
+    case kFromEsc: return occ_par_for<kFromEsc, false>(J, waves, seg);
+    case kFromPath: return occ_par_for<kFromPath, false>(J, waves, seg);
+    default: return occ_par_for<kFromPerm, false>(J, waves, seg);
   }
 }
 

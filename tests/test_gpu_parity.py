@@ -122,6 +122,16 @@ def test_parallel_in_time_fp64_passes(ctx, L):
             for k in ("status", "fail_step", "esc_step"):
                 assert np.array_equal(a[k], z[k]), (precision, mode, k)
             assert np.array_equal(a["path"], z["path"], equal_nan=True), (precision, mode)
+    try:
+        for seg in (4, 16):   # hand-over segment widths besides the default 8
+            ctx.set_option("seg64", seg)
+            z = _np(ctx.simulate(db, T=200, precision=L.FP32_RECHECK, write=L.WRITE_ALL, path_dtype=L.F64))
+            a = res[0, L.FP32_RECHECK]
+            for k in ("status", "fail_step", "esc_step"):
+                assert np.array_equal(a[k], z[k]), (seg, k)
+            assert np.array_equal(a["path"], z["path"], equal_nan=True), seg
+    finally:
+        ctx.set_option("seg64", 8)
     ref = oracle.simulate(b, T=200, path=True, nthreads=NTH)
     z = res[2, L.FP64]
     assert np.array_equal(z["status"], ref["status"]) and np.array_equal(z["fail_step"], ref["fail_step"])
