@@ -102,6 +102,9 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
 
   int cand = -1, item = 0, t = 0, t_end = 0, D = 0, n = 0, out_slot = 0;
   int t_back = 0x7FFF;  // hand-over pass: step from which the candidate returns to FP32
+  uint32_t sw[16];    // kFromPath: the current group of output positions (64 bytes)
+#pragma unroll
+  for (int i = 0; i < 16; ++i) sw[i] = 0u;
   int64_t row = -1;  // path row (kFromPath)
   bool redundant = false;
   double px = 0, py = 0, vx = 0, vy = 0, deg_thr = 0, drift_thr = 0;
@@ -336,7 +339,7 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
       }
       if (fail == 0 && redundant && drift_check(A, cand, item, D, n, P, bd, tid, drift_thr)) fail = 3;
       bool done = false;
-      if (SRC == kFromPath) {
+      if (SRC == kFromPath && DMAX > 5) {
         double2 po = P[out_slot * bd + tid];
         if (fail != 0) po = make_double2(__builtin_nan(""), __builtin_nan(""));
         const int t_stop = fail != 0 ? t_end : t + 1;
@@ -347,6 +350,66 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
             reinterpret_cast<double2*>(A.path)[row * T + tt] = po;
           else
             reinterpret_cast<float2*>(A.path)[row * T + tt] = make_float2((float)po.x, (float)po.y);
+        }
+        if (fail != 0 || ++t >= t_end) done = true;
+      } else if (SRC == kFromPath) {
+        // small mechanisms (few FLOP per path byte): the row is written 64 bytes at
+        // a time, the last K steps' positions staged in registers (K = 8 for f32
+        // paths, 4 for f64) and stored together
+        const int K = A.path_f64 ? 4 : 8;
+        const int k = t & (K - 1);
+        const int t_first = t - k;
+        int staged = k;  // entries of the group already staged (steps t_first .. t - 1)
+        if (fail == 0) {
+          const double2 po = P[out_slot * bd + tid];
+          // the entry's dwords: 4 for an f64 position, 2 for an f32 one
+          if (A.path_f64) {
+            const uint32_t v[4] = {(uint32_t)__double2loint(po.x), (uint32_t)__double2hiint(po.x),
+                                   (uint32_t)__double2loint(po.y), (uint32_t)__double2hiint(po.y)};
+#pragma unroll
+            for (int i = 0; i < 16; ++i) sw[i] = i / 4 == k ? v[i % 4] : sw[i];
+          } else {
+            const uint32_t v[2] = {__float_as_uint((float)po.x), __float_as_uint((float)po.y)};
+#pragma unroll
+            for (int i = 0; i < 16; ++i) sw[i] = i / 2 == k ? v[i % 2] : sw[i];
+          }
+          staged = k + 1;
+        }
+        const bool flush = fail != 0 || staged == K || t + 1 >= t_end;
+        if (flush && staged > 0) {
+          if (staged == K && (A.path_f64 || (T & 1) == 0)) {
+            // a whole group: four 16-byte stores (16-byte aligned: t_first is a
+            // multiple of K and rows of an even T start on 16 bytes)
+            uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<char*>(A.path) +
+                                                  (size_t)(row * T + t_first) * (A.path_f64 ? 16 : 8));
+#pragma unroll
+            for (int j = 0; j < 4; ++j) dst[j] = make_uint4(sw[4 * j], sw[4 * j + 1], sw[4 * j + 2], sw[4 * j + 3]);
+          } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              if (j < staged) {
+                if (A.path_f64) {
+                  if (j < 4)
+                    reinterpret_cast<double2*>(A.path)[row * T + t_first + j] = make_double2(
+                        __hiloint2double(sw[4 * j + 1], sw[4 * j]), __hiloint2double(sw[4 * j + 3], sw[4 * j + 2]));
+                } else {
+                  reinterpret_cast<float2*>(A.path)[row * T + t_first + j] =
+                      make_float2(__uint_as_float(sw[2 * j]), __uint_as_float(sw[2 * j + 1]));
+                }
+              }
+            }
+          }
+        }
+        if (fail != 0) {
+          // a failure here (possible only within rounding of a threshold) leaves the
+          // rest of the row NaN
+          const double nan = __builtin_nan("");
+          for (int tt = t; tt < t_end; ++tt) {
+            if (A.path_f64)
+              reinterpret_cast<double2*>(A.path)[row * T + tt] = make_double2(nan, nan);
+            else
+              reinterpret_cast<float2*>(A.path)[row * T + tt] = make_float2((float)nan, (float)nan);
+          }
         }
         if (fail != 0 || ++t >= t_end) done = true;
       } else if (fail != 0) {

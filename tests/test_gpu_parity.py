@@ -243,6 +243,24 @@ def test_step_counts(ctx, L, T):
     _fp32_parity(ctx, L, b, T=T, label=f"T={T}")
 
 
+@pytest.mark.parametrize("T", [1, 7, 8, 13, 200, 201])
+def test_small_mechanism_path_rows(ctx, L, T):
+    """Path rows of small mechanisms (written in 64-byte groups): every row,
+    including rows that end in a lock (NaN from the failing step) and step counts
+    that are not a multiple of the group, equal the oracle's in f64 and its
+    rounding in f32."""
+    _say(f"[rows] T={T}")
+    b = gen.workload("fourbar_u", 3000, seed=61)
+    db = L.to_device(b)
+    ref = oracle.simulate(b, T=T, path=True, nthreads=NTH)
+    r64 = _np(ctx.simulate(db, T=T, precision=L.FP64, write=L.WRITE_ALL, path_dtype=L.F64))
+    assert np.array_equal(r64["status"], ref["status"])
+    assert np.array_equal(r64["path"], ref["path"], equal_nan=True)
+    r32 = _np(ctx.simulate(db, T=T, precision=L.FP64, write=L.WRITE_ALL, path_dtype=L.F32))
+    assert np.array_equal(r32["path"], ref["path"].astype(np.float32), equal_nan=True)
+    assert np.isnan(ref["path"]).any() or T < 8
+
+
 def test_ragged_and_wide_strides(ctx, L):
     _say("[strides]")
     for J, lo, hi in ((7, 4, 7), (13, 6, 13), (32, 20, 32)):
