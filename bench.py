@@ -289,6 +289,66 @@ def stream_config(args, L, gen, oracle, tune, dev, threads):
             "d2h_GBps": stats["d2h_bytes"] / wall / 1e9, "sample_parity": par}
 
 
+def next_config(args, L, gen):
+    """The paper's infeasibility scale (samples per valid mechanism against the
+    joint count, "Scale of Infeasibilities") with on-device generation, and the
+    low-fidelity screen's cost and disagreement with the full run."""
+    import torch
+    import oracle
+    dev = torch.device("cuda:0")
+    T = args.T
+    threads = min(os.cpu_count() or 1, 64)
+    ctx = L.Context(0)
+    per_n = 2_000_000
+    table = {}
+    for paper in (False, True):
+        rows = []
+        for n in range(4, 21):
+            db = ctx.generate_dyads(per_n, seed=900 + n, J=20, n_lo=n, n_hi=n, paper_mode=paper)
+            r = ctx.simulate(db, T=T)
+            st = r["status"].cpu().numpy()
+            valid = int((st == 0).sum())
+            row = {"n": n, "candidates": per_n, "valid": valid,
+                   "samples_per_valid": (per_n / valid) if valid else None,
+                   "wasted": 1.0 - valid / per_n}
+            if n in (6, 12, 20):
+                # the first 20,000 against the oracle, decisions outside the bands
+                k = 20_000
+                sub = gen.dyad_batch(k, 900 + n, gen.n_uniform(n, n), J=20, paper_mode=paper)  # the same draws
+                if paper:
+                    sub = gen.standardize_paper(sub)  # as the device generator places pivot and tip
+                ref = oracle.simulate(sub, T=T, margins=True, nthreads=threads)
+                clear = ~oracle.in_band(ref["margins"])
+                row["oracle_sample"] = {"candidates": k, "out_of_band": int(clear.sum()),
+                                        "status_equal": float((st[:k][clear] == ref["status"][clear]).mean())}
+            rows.append(row)
+            log(f"{'paper' if paper else 'dyad'} n={n}: {valid} valid of {per_n}")
+        table["paper_mode" if paper else "dyad"] = rows
+    # low-fidelity screen (50 positions, then 200 for the survivors) on the headline workload
+    host = gen.workload("dyad_6_20", args.B, seed=2)
+    db = L.to_device(host, dev)
+    full = ctx.simulate(db, T=T)
+    st_full = full["status"].cpu().numpy()
+    res = {}
+    for tp in (0, 50):
+        dt, passes, r = time_sim(ctx, db, reps=10, T=T, T_prefilter=tp)
+        res[tp] = (dt, r["status"].cpu().numpy())
+    st_pre = res[50][1]
+    return {"metric": "samples per valid mechanism vs joint count; low-fidelity screen",
+            "unit": "samples/valid", "config": {
+                "workload": f"{per_n} candidates per joint count n = 4..20 generated on the device (dyad "
+                            "operator; and the paper's mode with linkless ground joints and a standard "
+                            "actuator), x0~U[0,1)^2, T=200, FP32 with FP64 escalation"},
+            "infeasibility": table,
+            "prefilter": {"workload": f"{args.B} dyad_6_20 candidates", "T_low": 50,
+                          "ms_full": res[0][0] * 1e3, "ms_screened": res[50][0] * 1e3,
+                          "speedup": res[0][0] / res[50][0],
+                          "valid_full": int((st_full == 0).sum()), "valid_screened": int((st_pre == 0).sum()),
+                          "rejected_by_screen_but_valid": int(((st_full == 0) & (st_pre != 0)).sum()),
+                          "valid_by_screen_but_not": int(((st_full != 0) & (st_pre == 0)).sum()),
+                          "status_disagreement": float((st_full != st_pre).mean())}}
+
+
 def other_config(args, L, gen):
     """Secondary configurations (their own JSON line; not the headline)."""
     import torch
@@ -396,12 +456,13 @@ def main():
     ap.add_argument("--no-pipeline", action="store_true", help="skip the two-stream pipelined leg")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--chunks", type=int, default=25, help="cfg5: chunks of 4M candidates")
-    ap.add_argument("--config", choices=["cfg2", "cfg1", "cfg1x", "cfg3", "cfg5"], default="cfg2",
+    ap.add_argument("--config", choices=["cfg2", "cfg1", "cfg1x", "cfg3", "cfg5", "next"], default="cfg2",
                     help="cfg2: the headline (1M dyad-built, 6-20 joints); cfg1: 10k crank-rocker four-bars "
                          "(oracle, GPU FP64, GPU FP32+recheck); cfg1x: 10M four-bars writing every path "
                          "(HBM-write roofline); cfg3: 4M skewed joint counts; cfg5: a stream of "
                          "100M candidates generated on the device in 4M chunks, valid paths normalised "
-                         "and copied to the host")
+                         "and copied to the host; next: samples per valid mechanism against the joint "
+                         "count and the low-fidelity screen")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device (HBM traffic scale for counters)")
     args = ap.parse_args()
@@ -412,6 +473,9 @@ def main():
     import torch
     from paper_2208_14567_amd import gen, links as L
 
+    if args.config == "next":
+        print(json.dumps(next_config(args, L, gen)))
+        return
     if args.config != "cfg2":
         print(json.dumps(other_config(args, L, gen)))
         return
