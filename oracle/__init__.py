@@ -22,6 +22,7 @@ SRC = os.path.join(HERE, "links_ref.c")
 LIB = os.path.join(HERE, "liblinks_ref.so")
 
 VALID, LOCKED, DEGENERATE, DRIFT, UNSOLVABLE, BAD_MECH = range(6)
+BRANCH_CONTINUITY, BRANCH_ORIENTATION = 0, 1
 NORM_PCA, NORM_DIAMETER = 0, 1
 NF_CONSTANT, NF_ISOTROPIC, NF_SIGN_TIE, NF_DIAM_TIE = 1, 2, 4, 8
 
@@ -82,6 +83,9 @@ def lib():
         L.links_ref_solve_order.restype = ctypes.c_int
         L.links_ref_simulate.argtypes = [i32, i32, P, P, P, P, P, i32, i32, ctypes.c_double, P, P, P, P, P, i32]
         L.links_ref_simulate.restype = ctypes.c_int
+        L.links_ref_simulate_branch.argtypes = [i32, i32, P, P, P, P, P, i32, i32, ctypes.c_double, P, P, P, P, P,
+                                                i32, i32]
+        L.links_ref_simulate_branch.restype = ctypes.c_int
         L.links_ref_normalize_paths.argtypes = [P, i32, i32, i32, P, P]
         L.links_ref_normalize_paths.restype = ctypes.c_int
         L.links_ref_curate.argtypes = [i32, P, P, P, P, i32, P, i32, P, i32, ctypes.c_double, P, P, P]
@@ -113,9 +117,11 @@ def solve_order(batch):
 
 
 def simulate(batch, T: int = 200, out_joint: int = -1, tau_drift: float = TAU_DRIFT, path: bool = False,
-             pos_all: bool = False, margins: bool = False, nthreads: int = 1, x0=None):
+             pos_all: bool = False, margins: bool = False, nthreads: int = 1, x0=None,
+             branch: int = BRANCH_CONTINUITY):
     """FP64 full-rotation simulation.  Returns a dict with status, fail_step and the
-    optional path [B,T,2], pos_all [B,T,J,2] and margins [B,4]."""
+    optional path [B,T,2], pos_all [B,T,J,2] and margins [B,4].  branch selects the
+    rule for the side of each placed joint (continuity or starting orientation)."""
     B, J = batch.B, batch.J
     st = np.empty(B, np.uint8)
     fs = np.empty(B, np.int16)
@@ -124,8 +130,8 @@ def simulate(batch, T: int = 200, out_joint: int = -1, tau_drift: float = TAU_DR
     mg = np.empty((B, 4), np.float64) if margins else None
     n, adj, fx, mo = _c(batch.n, np.uint8), _c(batch.adj, np.uint32), _c(batch.fixed, np.uint32), _c(batch.motor, np.uint8)
     xx = _c(batch.x0 if x0 is None else x0, np.float64)
-    rc = lib().links_ref_simulate(B, J, _p(n), _p(adj), _p(fx), _p(mo), _p(xx), T, out_joint, tau_drift,
-                                  _p(st), _p(fs), _p(pa), _p(al), _p(mg), nthreads)
+    rc = lib().links_ref_simulate_branch(B, J, _p(n), _p(adj), _p(fx), _p(mo), _p(xx), T, out_joint, tau_drift,
+                                         _p(st), _p(fs), _p(pa), _p(al), _p(mg), nthreads, branch)
     if rc != 0:
         raise ValueError("links_ref_simulate: bad argument")
     return {"status": st, "fail_step": fs, "path": pa, "pos_all": al, "margins": mg}

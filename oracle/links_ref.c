@@ -17,7 +17,10 @@
  *     (Methodology, "Finding Valid Initial Positions").
  *   - each joint is placed from its two known parents by the textbook
  *     circle-circle intersection (the paper does not print the formula) and the
- *     branch is the intersection nearer the joint's previous position.
+ *     branch is the intersection nearer the joint's previous position; a variant
+ *     keeps every joint on the side of its parents' line where it starts (the
+ *     paper leaves the rule open: it takes the initial positions into account and
+ *     evaluates the actuator positions independently).
  *   - path normalisation (Methodology, "Dataset Curation & Processing"): the
  *     diameter rule, plus a centroid / RMS / principal-axis variant.
  *
@@ -144,6 +147,7 @@ typedef struct {
   double* path;
   double* pos_all;
   double* margins;
+  int32_t branch; /* LREF_BRANCH_CONTINUITY or LREF_BRANCH_ORIENTATION */
 } sim_args;
 
 static double sq_dist(const double* p, const double* q) {
@@ -223,6 +227,15 @@ static void simulate_one(const sim_args* A, int32_t c) {
     prev[i][0] = x0[2 * i];
     prev[i][1] = x0[2 * i + 1];
   }
+  /* orientation rule: the side of a->b on which each placed joint starts
+   * (z of (x0_b - x0_a) x (x0_k - x0_a) >= 0: left, ties left) */
+  int left0[MAXJ];
+  for (int s = 0; s < nd; s++) {
+    int k = order[3 * s], a = order[3 * s + 1], b = order[3 * s + 2];
+    double cr = (x0[2 * b] - x0[2 * a]) * (x0[2 * k + 1] - x0[2 * a + 1]) -
+                (x0[2 * b + 1] - x0[2 * a + 1]) * (x0[2 * k] - x0[2 * a]);
+    left0[s] = cr >= 0.0;
+  }
 
   for (int t = 0; t < T; t++) {
     /* actuator: fixed joints stay at x0, the tip turns by theta_t about the pivot */
@@ -272,12 +285,19 @@ static void simulate_one(const sim_args* A, int32_t c) {
       double oy = (h / d) * dx;
       double cpx = bx + ox, cpy = by + oy; /* left of a->b */
       double cmx = bx - ox, cmy = by - oy; /* right of a->b */
-      /* branch: the intersection nearer the previous position (tie: left) */
-      double dp2 = (prev[k][0] - cpx) * (prev[k][0] - cpx) + (prev[k][1] - cpy) * (prev[k][1] - cpy);
-      double dm2 = (prev[k][0] - cmx) * (prev[k][0] - cmx) + (prev[k][1] - cmy) * (prev[k][1] - cmy);
-      double side = fabs((prev[k][0] - bx) * (-dy) + (prev[k][1] - by) * dx) / d;
-      if (side / scale < m_branch) m_branch = side / scale;
-      if (dp2 <= dm2) {
+      /* branch: the intersection nearer the previous position (tie: left), or
+       * the starting side of a->b */
+      int left;
+      if (A->branch == LREF_BRANCH_ORIENTATION) {
+        left = left0[s];
+      } else {
+        double dp2 = (prev[k][0] - cpx) * (prev[k][0] - cpx) + (prev[k][1] - cpy) * (prev[k][1] - cpy);
+        double dm2 = (prev[k][0] - cmx) * (prev[k][0] - cmx) + (prev[k][1] - cmy) * (prev[k][1] - cmy);
+        double side = fabs((prev[k][0] - bx) * (-dy) + (prev[k][1] - by) * dx) / d;
+        if (side / scale < m_branch) m_branch = side / scale;
+        left = dp2 <= dm2;
+      }
+      if (left) {
         pos[k][0] = cpx;
         pos[k][1] = cpy;
       } else {
@@ -350,10 +370,20 @@ int links_ref_simulate(int32_t B, int32_t J, const uint8_t* n, const uint32_t* a
                        int32_t T, int32_t out_joint, double tau_drift, uint8_t* status,
                        int16_t* fail_step, double* path,
                        double* pos_all, double* margins, int32_t nthreads) {
+  return links_ref_simulate_branch(B, J, n, adj, fixed, motor, x0, T, out_joint, tau_drift, status, fail_step,
+                                   path, pos_all, margins, nthreads, LREF_BRANCH_CONTINUITY);
+}
+
+int links_ref_simulate_branch(int32_t B, int32_t J, const uint8_t* n, const uint32_t* adj,
+                              const uint32_t* fixed, const uint8_t* motor, const double* x0,
+                              int32_t T, int32_t out_joint, double tau_drift, uint8_t* status,
+                              int16_t* fail_step, double* path,
+                              double* pos_all, double* margins, int32_t nthreads, int32_t branch) {
   if (B < 0 || J < 1 || J > MAXJ || T < 1 || out_joint >= J) return -1;
+  if (branch != LREF_BRANCH_CONTINUITY && branch != LREF_BRANCH_ORIENTATION) return -1;
   if (B > 0 && (!n || !adj || !fixed || !motor || !x0 || !status || !fail_step)) return -1;
   sim_args args = {B, J, T, out_joint, n, adj, fixed, motor, x0, tau_drift,
-                   status, fail_step, path, pos_all, margins};
+                   status, fail_step, path, pos_all, margins, branch};
   if (nthreads <= 1 || B < 2) {
     for (int32_t c = 0; c < B; c++) simulate_one(&args, c);
     return 0;

@@ -58,6 +58,18 @@ int links_ref_simulate(int32_t B, int32_t J, const uint8_t* n, const uint32_t* a
                        int16_t* fail_step, double* path,
                        double* pos_all, double* margins, int32_t nthreads);
 
+/* The same with the branch rule chosen: LREF_BRANCH_CONTINUITY (the intersection
+ * nearer the previous position, as links_ref_simulate) or LREF_BRANCH_ORIENTATION
+ * (every placed joint stays on the side of its parents' line a->b where it is in
+ * x0; margins[2] is then +inf).  Returns -1 for any other value. */
+#define LREF_BRANCH_CONTINUITY 0
+#define LREF_BRANCH_ORIENTATION 1
+int links_ref_simulate_branch(int32_t B, int32_t J, const uint8_t* n, const uint32_t* adj,
+                              const uint32_t* fixed, const uint8_t* motor, const double* x0,
+                              int32_t T, int32_t out_joint, double tau_drift, uint8_t* status,
+                              int16_t* fail_step, double* path,
+                              double* pos_all, double* margins, int32_t nthreads, int32_t branch);
+
 /* Path normalisation in FP64.  paths, out: [P][T][2]; xform: [P][5] =
  * (cx, cy, s, phi, flags) such that out = R(-phi)(p - c)/s, plus (0.5, 0.5) in
  * DIAMETER mode. */
