@@ -43,7 +43,7 @@ def _sides_and_mirror_gap(b, r, order, nd, c, T):
 
 def test_rules_keep_their_invariants():
     T = 60
-    b = gen.dyad_batch(400, 17, gen.n_uniform(5, 9), J=10)
+    b = gen.dyad_batch(200, 17, gen.n_uniform(5, 9), J=10)
     order, nd, _, _ = oracle.solve_order(b)
     rc = oracle.simulate(b, T=T, pos_all=True)
     ro = oracle.simulate(b, T=T, pos_all=True, branch=oracle.BRANCH_ORIENTATION)
@@ -52,7 +52,7 @@ def test_rules_keep_their_invariants():
         if nd[c] == 0:
             continue
         s_o, _ = _sides_and_mirror_gap(b, ro, order, nd, c, T)
-        if len(s_o):
+        if s_o.size:
             # orientation: the starting sides at every step
             x0 = b.x0[c]
             start = []
@@ -62,7 +62,7 @@ def test_rules_keep_their_invariants():
                 start.append(u[0] * (x0[k, 1] - x0[a, 1]) - u[1] * (x0[k, 0] - x0[a, 0]) >= 0)
             assert (s_o == np.array(start)[None, :]).all(), c
         _, n_c = _sides_and_mirror_gap(b, rc, order, nd, c, T)
-        assert n_c.all(), c  # continuity: never the farther intersection
+        assert n_c.size == 0 or n_c.all(), c  # continuity: never the farther intersection
         if rc["status"][c] != ro["status"][c] or rc["fail_step"][c] != ro["fail_step"][c]:
             differ += 1
     assert differ > 0  # the rules are different rules
@@ -75,7 +75,7 @@ def test_rules_agree_where_continuity_keeps_the_starting_sides():
     qualify; a coupler point almost on its parents' line may change side under
     continuity)."""
     T = 200
-    b = gen.workload("fourbar", 600, seed=9)
+    b = gen.workload("fourbar", 300, seed=9)
     order, nd, _, _ = oracle.solve_order(b)
     rc = oracle.simulate(b, T=T, path=True, pos_all=True)
     ro = oracle.simulate(b, T=T, path=True, branch=oracle.BRANCH_ORIENTATION)
@@ -88,7 +88,7 @@ def test_rules_agree_where_continuity_keeps_the_starting_sides():
             k, a, bb = (int(v) for v in order[c, s])
             u = x0[bb] - x0[a]
             start.append(u[0] * (x0[k, 1] - x0[a, 1]) - u[1] * (x0[k, 0] - x0[a, 0]) >= 0)
-        if (sides == np.array(start)[None, :]).all():
+        if sides.size == 0 or (sides == np.array(start)[None, :]).all():
             qualified += 1
             assert rc["status"][c] == ro["status"][c] and rc["fail_step"][c] == ro["fail_step"][c], c
             assert np.array_equal(rc["path"][c], ro["path"][c], equal_nan=True), c

@@ -12,12 +12,14 @@ from tests import test_oracle_fixtures as fx
 from tests import test_oracle_fourbar as fb
 from tests import test_oracle_curate as cu
 from tests import test_oracle_order as od
+from tests import test_oracle_branch as br
 
 MUTATIONS = {
     "offset_sign": ("double ox = -(h / d) * dy;", "double ox = (h / d) * dy;"),
     "swapped_radii": ("double along = (d2 + ra2 - rb2) / (2.0 * d);", "double along = (d2 - ra2 + rb2) / (2.0 * d);"),
     "foot_over_d2": ("double along = (d2 + ra2 - rb2) / (2.0 * d);", "double along = (d2 + ra2 - rb2) / (2.0 * d2);"),
-    "branch_inverted": ("if (dp2 <= dm2) {", "if (dp2 > dm2) {"),
+    "branch_inverted": ("left = dp2 <= dm2;", "left = dp2 > dm2;"),
+    "orientation_flipped": ("left0[s] = cr >= 0.0;", "left0[s] = cr < 0.0;"),
     "clockwise_crank": ("double theta = 2.0 * M_PI * (double)t / (double)T;",
                         "double theta = -2.0 * M_PI * (double)t / (double)T;"),
     "tip_y_sign": ("pos[tip][1] = x0[2 * pivot + 1] + (st * vx + ct * vy);",
@@ -49,6 +51,8 @@ PINS = [
     lambda: cu.test_fourbar_arcs_circles_and_reduction(None),
     lambda: cu.test_radial_variance_of_an_ellipse(None),
     lambda: cu.test_reduced_mechanism_reproduces_the_path(None),
+    br.test_rules_keep_their_invariants,
+    br.test_rules_agree_where_continuity_keeps_the_starting_sides,
 ]
 
 
