@@ -143,7 +143,17 @@ typedef struct {
                         * that fail keep that status, with fail_step converted to the
                         * same angle on the T grid (t * T / T_prefilter) and
                         * esc_step -1, and only the survivors are simulated at T */
+  int32_t branch;      /* side of each placed joint, which the paper leaves open
+                        * (Methodology, "Graphical Simulator"; "Computational Cost of
+                        * Simulations"): LINKS_BRANCH_CONTINUITY (default) the
+                        * intersection nearer the joint's previous position (ties:
+                        * left of a->b); LINKS_BRANCH_ORIENTATION the side of its
+                        * parents' line a->b on which the joint lies in x0 (decided
+                        * once per candidate in FP64, so no band is needed for it) */
 } links_sim_opts;
+
+#define LINKS_BRANCH_CONTINUITY 0
+#define LINKS_BRANCH_ORIENTATION 1
 
 /* Fills opts with the defaults above (T = 200, WRITE_NONE, F32). */
 void links_sim_opts_default(links_sim_opts* opts);

@@ -243,6 +243,7 @@ void links_sim_opts_default(links_sim_opts* o) {
   o->write = LINKS_WRITE_NONE;
   o->path_dtype = LINKS_F32;
   o->T_prefilter = 0;
+  o->branch = LINKS_BRANCH_CONTINUITY;
 }
 
 int links_set_tuning(links_ctx* ctx, int waves32, int refill_min, int waves64) {
@@ -378,6 +379,8 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   if (opts->write < 0 || opts->write > 2) return fail(LINKS_ERR_ARG, "bad write mode %d", opts->write);
   if (opts->path_dtype != LINKS_F32 && opts->path_dtype != LINKS_F64)
     return fail(LINKS_ERR_ARG, "bad path dtype %d", opts->path_dtype);
+  if (opts->branch != LINKS_BRANCH_CONTINUITY && opts->branch != LINKS_BRANCH_ORIENTATION)
+    return fail(LINKS_ERR_ARG, "bad branch rule %d", opts->branch);
   if (opts->out_joint < -1 || opts->out_joint >= J)
     return fail(LINKS_ERR_ARG, "out_joint %d outside [-1, J)", opts->out_joint);
   if (!(opts->eps_disc >= 0) || !(opts->eps_branch >= 0) || !(opts->tau_drift >= 0))
@@ -568,6 +571,7 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   sa.deesc = 0;
   sa.resume = 0;
   sa.chunk = ctx->chunk;
+  sa.branch = opts->branch;
 
   LaunchCfg c64;
   c64.waves = ctx->waves64;

@@ -39,7 +39,8 @@ struct CandF32 {
   float TS;      // 2 scale, a bound on 2 ra in the branch error term
   float u;       // relative rounding unit of a placement
   float DG;      // degenerate threshold 1e-12 scale^2 (FP32-only mode)
-  float pad[4];
+  uint32_t side; // bit s: placed joint s starts left of its parents' line a->b
+  float pad[3];
 };
 
 // FP64 constants of one candidate
@@ -48,7 +49,7 @@ struct CandF64 {
   double scale;
   double deg_thr;  // 1e-12 scale^2
   double drift_thr;  // tau scale
-  double pad;
+  uint64_t side;     // as CandF32::side
 };
 
 // FP32 per-entry constants, rounded from FP64: S = (ra + rb)^2, Dm = (ra - rb)^2,
@@ -112,6 +113,7 @@ struct SimArgs {
   int32_t refill_min;  // refill a wave when at least this many lanes are idle
   int32_t spread;      // FP32 pass: waves start spread over the buckets (1) or all in the largest (0)
   int32_t chunk;       // items a wave claims with one atomic
+  int32_t branch;      // LINKS_BRANCH_CONTINUITY or LINKS_BRANCH_ORIENTATION (side bits of the records)
   // returning to FP32 after a hand-over: the FP64 pass stops a candidate deesc
   // steps after its hand-over step and queues it (res, res_pos); a resume round of
   // the FP32 pass (resume = 1) takes its work items from that queue

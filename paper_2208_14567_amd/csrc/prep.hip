@@ -495,6 +495,15 @@ __global__ void __launch_bounds__(kSortBlock) fill_kernel(PrepArgs A) {
   A.meta[p] = m;
   A.perm[p] = c;
 
+  // starting side of every placed joint (bit s: left of a->b, ties left), the
+  // oracle's cross product evaluated in the same order
+  uint32_t side = 0u;
+  for (int s = 0; s < D; s++) {
+    const uint32_t e = ord_l[s * kSortBlock + tid];
+    const int k = e & 0xFF, a = (e >> 8) & 0xFF, b = (e >> 16) & 0xFF;
+    const double cr = (row.x(b) - row.x(a)) * (row.y(k) - row.y(a)) - (row.y(b) - row.y(a)) * (row.x(k) - row.x(a));
+    side |= cr >= 0.0 ? (1u << s) : 0u;
+  }
   const double px = row.x(pivot), py = row.y(pivot);
   const double vx = row.x(tip) - px, vy = row.y(tip) - py;
   const double scale2 = scale * scale;
@@ -506,7 +515,7 @@ __global__ void __launch_bounds__(kSortBlock) fill_kernel(PrepArgs A) {
   cd.scale = scale;
   cd.deg_thr = 1e-12 * scale2;
   cd.drift_thr = A.tau_drift * scale;
-  cd.pad = 0.0;
+  cd.side = side;
   A.cd[p] = cd;
 
   // FP32 thresholds and error units: a computed position carries at most a few
@@ -525,7 +534,8 @@ __global__ void __launch_bounds__(kSortBlock) fill_kernel(PrepArgs A) {
   cf.TS = (float)(2.0 * scale);
   cf.u = (float)u;
   cf.DG = (float)(1e-12 * scale2);
-  cf.pad[0] = cf.pad[1] = cf.pad[2] = cf.pad[3] = 0.f;
+  cf.side = side;
+  cf.pad[0] = cf.pad[1] = cf.pad[2] = 0.f;
   A.cf[p] = cf;
 
   for (int s = 0; s < D; s++) {

@@ -62,6 +62,8 @@ sim32_kernel(SimArgs A) {
   float px = 0.f, py = 0.f, vx = 0.f, vy = 0.f, U = 0.f, KB = 0.f, CD = 0.f, EB = 0.f;
   float U2 = 0.f, TS = 0.f, uu = 0.f, DG = 0.f;
   bool force64 = false;
+  const bool orient = A.branch != 0;  // sides fixed at the start (else continuity)
+  uint32_t obits = 0u;                // starting side of each placed joint
   int dmax_w = 0;  // largest solve order among the wave's lanes (uniform)
   float cS[DMAX], cDm[DMAX], cKc[DMAX];
   uint32_t cSl[(DMAX + 1) / 2];  // parent slots, two entries per register
@@ -224,6 +226,7 @@ sim32_kernel(SimArgs A) {
           TS = f.TS;
           uu = f.u;
           DG = f.DG;
+          obits = f.side;
 #pragma unroll
           for (int s = 0; s < DMAX; ++s) {
             if (s < D) {
@@ -318,7 +321,9 @@ sim32_kernel(SimArgs A) {
       const float ox = -be * dy, oy = be * dx;      // left normal, length h
       // branch: the intersection nearer the previous position
       const float sg = fmaf(pr.x - bx, ox, (pr.y - by) * oy);
-      const float sgn = sg >= 0.f ? 1.f : -1.f;
+      // continuity: the side of the previous position; orientation: the starting side
+      const bool left = orient ? ((obits >> s) & 1u) != 0u : sg >= 0.f;
+      const float sgn = left ? 1.f : -1.f;
       const float nx = fmaf(sgn, ox, bx), ny = fmaf(sgn, oy, by);
       bool write;
       float Ek = 0.f, Ep = 0.f;
@@ -333,7 +338,7 @@ sim32_kernel(SimArgs A) {
         const float sensK = 4.f * d * fabsf(fmaf(0.5f, S + Dm, -d2));
         const float kthr = fmaf(sensK, Eab, KB);
         const float mthr = fmaf(Eab, fmaf(TS, rd, 1.f), EB + Ep);
-        const bool band = (int)(fabsf(K) < kthr) | (int)(d2 < CD) | (int)(fabsf(sg) < mthr * h);
+        const bool band = (int)(fabsf(K) < kthr) | (int)(d2 < CD) | (int)(!orient && fabsf(sg) < mthr * h);
         const bool lock = K < 0.f;
         lock_ev = lock_ev | (act & !band & lock);
         ev = ev | (act & (band | lock));
@@ -480,6 +485,8 @@ __global__ void __launch_bounds__(256) simpar32_kernel(SimArgs A) {
   float px = 0.f, py = 0.f, vx = 0.f, vy = 0.f, U = 0.f, KB = 0.f, CD = 0.f, EB = 0.f;
   float U2 = 0.f, TS = 0.f, uu = 0.f, DG = 0.f;
   int dmax_w = 0;
+  const bool orient = A.branch != 0;  // sides fixed at the start (else continuity)
+  uint32_t obits = 0u;
   // next candidate: claimed (need_next false), loaded into registers during a
   // pass (in_flight), then staged in LDS (has_staged) until the segment is free
   bool need_next = true, in_flight = false, has_staged = false;
@@ -524,6 +531,7 @@ __global__ void __launch_bounds__(256) simpar32_kernel(SimArgs A) {
         TS = CFN[9];
         uu = CFN[10];
         DG = CFN[11];
+        obits = __float_as_uint(CFN[12]);  // CandF32::side
         cpar ^= 1;
         t0 = 0;
         fresh = true;
@@ -558,7 +566,7 @@ __global__ void __launch_bounds__(256) simpar32_kernel(SimArgs A) {
       }
       const uint64_t gb0 = __ballot(g0), gb1 = __ballot(g1);
       if (fill) {
-        ori = (uint32_t)((gb0 >> seg0) & 0xFFFFu) | ((uint32_t)((gb1 >> seg0) & 0xFFFFu) << kSeg32);
+        ori = orient ? obits : (uint32_t)((gb0 >> seg0) & 0xFFFFu) | ((uint32_t)((gb1 >> seg0) & 0xFFFFu) << kSeg32);
         ori_prov = ori;
       }
       int dm = cand >= 0 ? D : 0;
@@ -696,10 +704,10 @@ __global__ void __launch_bounds__(256) simpar32_kernel(SimArgs A) {
             const bool rule_left = sg >= 0.f;
             if ((MODE & 1) == 0) {
               const float mthr = fmaf(Eab, fmaf(TS, rd, 1.f), EB + Ep);
-              const bool band = bK | (fabsf(sg) < mthr * h);
-              ev = band ? kE32Band : lock ? kE32Lock : rule_left != left ? kE32Side : kE32None;
+              const bool band = bK | (!orient && fabsf(sg) < mthr * h);
+              ev = band ? kE32Band : lock ? kE32Lock : (!orient && rule_left != left) ? kE32Side : kE32None;
             } else {
-              ev = deg ? kE32Degenerate : lock ? kE32Lock : rule_left != left ? kE32Side : kE32None;
+              ev = deg ? kE32Degenerate : lock ? kE32Lock : (!orient && rule_left != left) ? kE32Side : kE32None;
             }
             ev_s = s;
           }

@@ -107,6 +107,8 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
   for (int i = 0; i < 16; ++i) sw[i] = 0u;
   int64_t row = -1;  // path row (kFromPath)
   bool redundant = false;
+  const bool orient = A.branch != 0;  // sides fixed at the start (else continuity)
+  uint32_t obits = 0u;                // starting side of each placed joint
   double px = 0, py = 0, vx = 0, vy = 0, deg_thr = 0, drift_thr = 0;
   bool exhausted = false;
   // per-entry constants of the lane's candidate, held in registers: S, Dm and
@@ -209,6 +211,7 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
             vy = f.vy;
             deg_thr = f.deg_thr;
             drift_thr = f.drift_thr;
+            obits = (uint32_t)f.side;
 #pragma unroll
             for (int s = 0; s < DMAX; ++s) {
               if (s < D) {
@@ -311,7 +314,8 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
                 const double cmx = bx - ox, cmy = by - oy;
                 const double dp2 = (pr.x - cpx) * (pr.x - cpx) + (pr.y - cpy) * (pr.y - cpy);
                 const double dm2 = (pr.x - cmx) * (pr.x - cmx) + (pr.y - cmy) * (pr.y - cmy);
-                P[s * bd + tid] = dp2 <= dm2 ? make_double2(cpx, cpy) : make_double2(cmx, cmy);
+                const bool left = orient ? ((obits >> s) & 1u) != 0u : dp2 <= dm2;
+                P[s * bd + tid] = left ? make_double2(cpx, cpy) : make_double2(cmx, cmy);
               }
             }
           } else {
@@ -331,7 +335,8 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
               const double bx = fma(al, dx, pa.x), by = fma(al, dy, pa.y);
               const double ox = -be * dy, oy = be * dx;
               const double sg = fma(pr.x - bx, ox, (pr.y - by) * oy);
-              const double sgn = sg >= 0.0 ? 1.0 : -1.0;
+              const bool left = orient ? ((obits >> s) & 1u) != 0u : sg >= 0.0;
+              const double sgn = left ? 1.0 : -1.0;
               P[s * bd + tid] = make_double2(fma(sgn, ox, bx), fma(sgn, oy, by));
             }
           }
@@ -545,6 +550,8 @@ __global__ void __launch_bounds__(256) simpar64_kernel(SimArgs A) {
   int cand = -1, item = 0, t0 = 0, t_end = 0, D = 0, n = 0, out_slot = 0, restarts = 0;
   int64_t row = -1;
   bool redundant = false;
+  const bool orient = A.branch != 0;  // sides fixed at the start (else continuity)
+  uint32_t obits = 0u;
   bool fresh = false;             // the provider holds the starting positions
   uint32_t ori = 0u;              // side of every dyad for the computing lanes (bit set: left of a->b)
   uint32_t ori_prov = 0u;         // the sides in force at the provider's step
@@ -651,6 +658,7 @@ __global__ void __launch_bounds__(256) simpar64_kernel(SimArgs A) {
           vy = f.vy;
           deg_thr = f.deg_thr;
           drift_thr = f.drift_thr;
+          obits = (uint32_t)f.side;
           t0 = ts;
           fresh = true;
           restarts = 0;
@@ -693,7 +701,7 @@ __global__ void __launch_bounds__(256) simpar64_kernel(SimArgs A) {
         og |= (uint32_t)((__ballot(g) >> seg0) & WMASK) << (k * W);
       }
       if (fill) {
-        ori = og;
+        ori = orient ? obits : og;
         ori_prov = ori;
       }
       // largest solve order among the wave's segments (bounds the dyad loop)
@@ -785,7 +793,7 @@ __global__ void __launch_bounds__(256) simpar64_kernel(SimArgs A) {
         }
         // the previous step's position of this joint, from the left neighbour
         const double qx = row_prev(val.x), qy = row_prev(val.y);
-        if (placed && r > 0) {
+        if (placed && r > 0 && !orient) {
           bool rule_left;
           if (EXACT) {
             const double dp2 = (qx - rx0) * (qx - rx0) + (qy - ry0) * (qy - ry0);

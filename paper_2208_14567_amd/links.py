@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "liblinks.so")
 OK, ERR_ARG, ERR_DEVICE, ERR_OOM = 0, -1, -2, -3
 VALID, LOCKED, DEGENERATE, DRIFT, UNSOLVABLE, BAD_MECH = range(6)
 FP32_RECHECK, FP64, FP32_ONLY = 0, 1, 2
+BRANCH_CONTINUITY, BRANCH_ORIENTATION = 0, 1
 WRITE_NONE, WRITE_ALL, WRITE_VALID = 0, 1, 2
 F32, F64 = 0, 1
 NORM_PCA, NORM_DIAMETER = 0, 1
@@ -39,7 +40,7 @@ class Batch(ctypes.Structure):
 class SimOpts(ctypes.Structure):
     _fields_ = [("T", i32), ("precision", i32), ("eps_disc", ctypes.c_double), ("eps_branch", ctypes.c_double),
                 ("tau_drift", ctypes.c_double), ("out_joint", i32), ("write", i32), ("path_dtype", i32),
-                ("T_prefilter", i32)]
+                ("T_prefilter", i32), ("branch", i32)]
 
 
 class SimOut(ctypes.Structure):
@@ -232,7 +233,7 @@ class Context:
 
     # ------------------------------------------------------------------ simulation
     def _sim_args(self, b: DeviceBatch, T, precision, write, out_joint, path_dtype, cap, eps_disc, eps_branch,
-                  tau_drift, out, T_prefilter=0):
+                  tau_drift, out, T_prefilter=0, branch=BRANCH_CONTINUITY):
         dev = b.n.device
         B = b.B
         o = out or {}
@@ -249,7 +250,8 @@ class Context:
             path = o.get("path") if o.get("path") is not None else torch.empty((max(cap_v, 1), T, 2), dtype=pdt, device=dev)
             idx = o.get("path_index") if o.get("path_index") is not None else torch.empty(max(cap_v, 1), dtype=torch.int32, device=dev)
             nw = o.get("n_written") if o.get("n_written") is not None else torch.empty(1, dtype=torch.int32, device=dev)
-        opts = SimOpts(T, precision, eps_disc, eps_branch, tau_drift, out_joint, write, path_dtype, T_prefilter)
+        opts = SimOpts(T, precision, eps_disc, eps_branch, tau_drift, out_joint, write, path_dtype, T_prefilter,
+                       branch)
         so = SimOut(_ptr(status), _ptr(fail), _ptr(esc), _ptr(path), _ptr(idx), _ptr(nw), cap_v)
         res = {"status": status, "fail_step": fail, "esc_step": esc}
         if path is not None:
@@ -262,12 +264,13 @@ class Context:
     def simulate(self, b: DeviceBatch, T: int = 200, precision: int = FP32_RECHECK, write: int = WRITE_NONE,
                  out_joint: int = -1, path_dtype: int = F32, cap: Optional[int] = None, eps_disc: float = 1e-6,
                  eps_branch: float = 1e-5, tau_drift: float = 1e-4, out: Optional[dict] = None, stream=None,
-                 T_prefilter: int = 0):
+                 T_prefilter: int = 0, branch: int = BRANCH_CONTINUITY):
         """Returns a dict of device tensors: status, fail_step, esc_step and, by write
         mode, path ([B,T,2] or [cap,T,2]), path_index and n_written.  T_prefilter > 0
-        runs the low-fidelity check at that many positions first."""
+        runs the low-fidelity check at that many positions first; branch selects the
+        side rule (continuity or starting orientation)."""
         cb, opts, so, res = self._sim_args(b, T, precision, write, out_joint, path_dtype, cap, eps_disc, eps_branch,
-                                           tau_drift, out, T_prefilter)
+                                           tau_drift, out, T_prefilter, branch)
         _check(load().links_simulate(self._h, ctypes.byref(cb), ctypes.byref(opts), ctypes.byref(so), _stream(stream)),
                "links_simulate")
         return res

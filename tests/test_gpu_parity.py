@@ -146,17 +146,62 @@ def test_parallel_in_time_fp32_pass(ctx, L, precision):
     b = gen.workload("dyad_6_20", 30000, seed=22)
     db = L.to_device(b)
     res = {}
+    prev = ctx.get_option("par32")
     try:
         for mode in (0, 1):
             ctx.set_option("par32", mode)
             res[mode] = _np(ctx.simulate(db, T=200, precision=precision, write=L.WRITE_ALL, path_dtype=L.F64))
     finally:
-        ctx.set_option("par32", 1)
+        ctx.set_option("par32", prev)
     a, z = res[0], res[1]
     for k in ("status", "fail_step", "esc_step"):
         diff = np.nonzero(a[k] != z[k])[0]
         assert diff.size == 0, (k, diff[:10], a[k][diff[:10]], z[k][diff[:10]])
     assert np.array_equal(a["path"], z["path"], equal_nan=True)
+
+
+ORIENT_WORKLOADS = [("fourbar_u", 4000, 31), ("dyad_6_20", 20000, 32), ("paper_8_20", 6000, 33)]
+
+
+@pytest.mark.parametrize("name,B,seed", ORIENT_WORKLOADS)
+def test_orientation_rule_parity(ctx, L, name, B, seed):
+    """The orientation branch rule: FP64 bit-exact with the oracle's orientation
+    rule (statuses, steps, paths); FP32 with escalation equal to it outside the
+    bands, paths within 1e-5 of the scale."""
+    _say(f"[orientation] {name} B={B}")
+    b = gen.workload(name, B, seed=seed)
+    r = _np(ctx.simulate(L.to_device(b), T=200, precision=L.FP64, write=L.WRITE_ALL, path_dtype=L.F64,
+                         branch=L.BRANCH_ORIENTATION))
+    ref = oracle.simulate(b, T=200, path=True, nthreads=NTH, branch=oracle.BRANCH_ORIENTATION)
+    assert np.array_equal(r["status"], ref["status"]) and np.array_equal(r["fail_step"], ref["fail_step"])
+    assert np.array_equal(r["path"], ref["path"], equal_nan=True)
+    cont = oracle.simulate(b, T=200, nthreads=NTH)
+    _say(f"   statuses differing from the continuity rule: {(cont['status'] != ref['status']).mean():.4f}")
+    _fp32_parity(ctx, L, b, label=f"{name} orientation", branch=L.BRANCH_ORIENTATION)
+
+
+def test_orientation_rule_parallel_passes(ctx, L):
+    """Under the orientation rule the parallel-in-time passes (no side changes to
+    restart on) give the step-by-step results."""
+    b = gen.workload("dyad_4_20", 20000, seed=34)
+    db = L.to_device(b)
+    p32, p64 = ctx.get_option("par32"), ctx.get_option("par64")
+    res = {}
+    try:
+        for m32, m64 in ((0, 0), (1, 2)):
+            ctx.set_option("par32", m32)
+            ctx.set_option("par64", m64)
+            for precision in (L.FP64, L.FP32_RECHECK):
+                res[m32, precision] = _np(ctx.simulate(db, T=200, precision=precision, write=L.WRITE_ALL,
+                                                       path_dtype=L.F64, branch=L.BRANCH_ORIENTATION))
+    finally:
+        ctx.set_option("par32", p32)
+        ctx.set_option("par64", p64)
+    for precision in (L.FP64, L.FP32_RECHECK):
+        a, z = res[0, precision], res[1, precision]
+        for k in ("status", "fail_step", "esc_step"):
+            assert np.array_equal(a[k], z[k]), (precision, k)
+        assert np.array_equal(a["path"], z["path"], equal_nan=True), precision
 
 
 @pytest.mark.parametrize("J", [7, 10, 13, 20, 22, 32])
@@ -194,10 +239,10 @@ def test_fp64_bit_exact(ctx, L, name, B, seed):
     assert same.all(), f"{(~same.all(axis=(1, 2))).sum()} paths differ in some bit"
 
 
-def _fp32_parity(ctx, L, b, T=200, write=None, label=""):
+def _fp32_parity(ctx, L, b, T=200, write=None, label="", branch=0):
     write = L.WRITE_ALL if write is None else write
-    r = _np(ctx.simulate(L.to_device(b), T=T, precision=L.FP32_RECHECK, write=write))
-    ref = oracle.simulate(b, T=T, path=True, margins=True, nthreads=NTH)
+    r = _np(ctx.simulate(L.to_device(b), T=T, precision=L.FP32_RECHECK, write=write, branch=branch))
+    ref = oracle.simulate(b, T=T, path=True, margins=True, nthreads=NTH, branch=branch)
     ib = oracle.in_band(ref["margins"])
     clear = ~ib
     bad = clear & ((r["status"] != ref["status"]) | (r["fail_step"] != ref["fail_step"]))
