@@ -440,6 +440,111 @@ def other_config(args, L, gen):
                               "in_band_equal": float(agree[~clear].mean()) if (~clear).any() else None}}
 
 
+ALU_LANES = 256 * 64 * 2.4e9      # FP32 lane operations per second without packed FP32 (256 CUs, 64 lanes, 2.4 GHz)
+CHAMFER_OPS_PER_PAIR = 5          # two differences, square, fused square-add, one three-way minimum
+
+
+def retrieval_config(args, L, gen):
+    """The retrieval case study: a bank of curated DIAMETER-normalised coupler
+    paths (circles and arcs removed) of valid dyad-built mechanisms (n ~ U{6..20},
+    seed 7), generated, simulated, normalised and curated on the device, in
+    candidate order (random by construction, so the bank is already shuffled); three query paths from valid mechanisms of
+    another seed (8).  Timed: the top 3 over the whole bank (BEST, no cut-off),
+    and the scan in bank order until three paths below the 0.03 cut-off are found
+    (FIRST).  The oracle checks the answers and a sample of distances."""
+    import torch
+    import oracle
+    from oracle import retrieval as R
+    dev = torch.device("cuda:0")
+    T, P = args.T, args.bank
+    CH, cap = 4_000_000, 1_000_000
+    ctx = L.Context(0)
+    bank = torch.empty((P, T, 2), dtype=torch.float32, device=dev)
+    xf = torch.empty((cap, 5), dtype=torch.float32, device=dev)
+
+    norm = torch.empty((cap, T, 2), dtype=torch.float32, device=dev)
+
+    def valid_paths(seed, n_cand, first, out_rows, lo):
+        """Curated paths of one chunk: valid, DIAMETER-normalised, circles and arcs
+        removed (links_curate), appended to out_rows from row lo."""
+        b = ctx.generate_dyads(n_cand, seed, first=first)
+        r = ctx.simulate(b, T=T, write=L.WRITE_VALID, cap=cap)
+        n = min(int(r["n_written"][0]), cap)
+        if n == 0:
+            return 0
+        ctx.normalize_paths(r["path"][:n], L.NORM_DIAMETER, out=norm[:n], xform=xf[:n])
+        fl = ctx.curate(b, norm[:n], path_index=r["path_index"][:n])["flags"]
+        keep = norm[:n][fl == 0]
+        m = min(int(keep.shape[0]), out_rows.shape[0] - lo)
+        out_rows[lo:lo + m] = keep[:m]
+        return m
+
+    t0 = time.perf_counter()
+    filled, chunks = 0, 0
+    while filled < P:
+        filled += valid_paths(7, CH, chunks * CH, bank, filled)
+        chunks += 1
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    qbuf = torch.empty((64, T, 2), dtype=torch.float32, device=dev)
+    valid_paths(8, 20000, 0, qbuf, 0)
+    queries = qbuf[:3].contiguous()
+    log(f"bank: {P} valid paths from {chunks * CH} candidates in {build_s:.1f}s")
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            res = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps, res
+
+    best_s, (bidx, bdist) = timed(lambda: ctx.chamfer_search(bank, queries, k=3, cutoff=float("inf"),
+                                                             order=L.SEARCH_BEST), args.steps)
+    first_s, (fidx, fdist) = timed(lambda: ctx.chamfer_search(bank, queries, k=3, cutoff=R.CUTOFF,
+                                                              order=L.SEARCH_FIRST), args.steps)
+    pairs = 3 * P
+    rate = pairs / best_s
+    achieved = rate * T * T
+    peak = ALU_LANES / CHAMFER_OPS_PER_PAIR
+    # oracle: the returned answers and 300 sampled distances per query
+    hb = bank.cpu().numpy() if P <= 2_000_000 else None
+    qh = queries.cpu().numpy()
+    bi, bd, fi, fd = (x.cpu().numpy() for x in (bidx, bdist, fidx, fdist))
+    rng = np.random.default_rng(0)
+    errs, checked = [], 0
+    for q in range(3):
+        rows = np.concatenate([bi[q][bi[q] >= 0], fi[q][fi[q] >= 0], rng.choice(P, 300, replace=False)])
+        paths = bank[torch.from_numpy(rows).to(dev)].cpu().numpy() if hb is None else hb[rows]
+        want = R.chamfer_bank(qh[q], paths)
+        gotd = ctx.chamfer(torch.from_numpy(paths).to(dev), queries[q:q + 1]).cpu().numpy()[0]
+        errs.append(float(np.max(np.abs(gotd - want) / np.maximum(want, 1e-30))))
+        nb = int((bi[q] >= 0).sum())
+        errs.append(float(np.max(np.abs(bd[q][:nb] - want[:nb]) / np.maximum(want[:nb], 1e-30))))
+        checked += len(rows)
+    # CPU oracle on a bounded sample
+    cpu_n = 400
+    t = time.perf_counter()
+    R.chamfer_bank(qh[0], bank[:cpu_n].cpu().numpy())
+    cpu_rate = cpu_n / (time.perf_counter() - t)
+    scanned = [int(i[-1]) + 1 if i[-1] >= 0 else P for i in fi]
+    return {"metric": "chamfer path comparisons/sec (bank search)", "unit": "comparisons/s", "value": rate,
+            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"top-3 search of 3 query paths over {P} curated DIAMETER-normalised "
+                                   f"coupler paths of valid dyad-built mechanisms (n~U{{6..20}}), T={T}",
+                       "bank": P, "T": T, "queries": 3, "candidates_simulated": chunks * CH},
+            "best_ms": best_s * 1e3, "ms_per_query_full_bank": best_s * 1e3 / 3,
+            "first_ms": first_s * 1e3, "first_scanned": scanned, "first_idx": fi.tolist(),
+            "first_dist": fd.tolist(), "best_idx": bi.tolist(), "best_dist": bd.tolist(),
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "point pairs/s",
+                         "frac": achieved / peak, "ops_per_pair": CHAMFER_OPS_PER_PAIR},
+            "oracle_check": {"rows_checked": checked, "max_rel_err": max(errs)},
+            "cpu_baseline": {"value": cpu_rate, "unit": "comparisons/s", "cores": 1, "kind": "oracle",
+                             "sample": f"1 query against {cpu_n} bank paths (numpy float64)"},
+            "bank_build_s": build_s}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -456,13 +561,16 @@ def main():
     ap.add_argument("--no-pipeline", action="store_true", help="skip the two-stream pipelined leg")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--chunks", type=int, default=25, help="cfg5: chunks of 4M candidates")
-    ap.add_argument("--config", choices=["cfg2", "cfg1", "cfg1x", "cfg3", "cfg5", "next"], default="cfg2",
+    ap.add_argument("--bank", type=int, default=10_000_000, help="retrieval: bank paths")
+    ap.add_argument("--config", choices=["cfg2", "cfg1", "cfg1x", "cfg3", "cfg5", "next", "retrieval"],
+                    default="cfg2",
                     help="cfg2: the headline (1M dyad-built, 6-20 joints); cfg1: 10k crank-rocker four-bars "
                          "(oracle, GPU FP64, GPU FP32+recheck); cfg1x: 10M four-bars writing every path "
                          "(HBM-write roofline); cfg3: 4M skewed joint counts; cfg5: a stream of "
                          "100M candidates generated on the device in 4M chunks, valid paths normalised "
                          "and copied to the host; next: samples per valid mechanism against the joint "
-                         "count and the low-fidelity screen")
+                         "count and the low-fidelity screen; retrieval: chamfer search over a bank of "
+                         "normalised coupler paths")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device (HBM traffic scale for counters)")
     args = ap.parse_args()
@@ -475,6 +583,9 @@ def main():
 
     if args.config == "next":
         print(json.dumps(next_config(args, L, gen)))
+        return
+    if args.config == "retrieval":
+        print(json.dumps(retrieval_config(args, L, gen)))
         return
     if args.config != "cfg2":
         print(json.dumps(other_config(args, L, gen)))

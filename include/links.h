@@ -286,6 +286,38 @@ int links_curate(links_ctx* ctx, const links_batch* batch, const int32_t* path_i
                  int32_t cap, int32_t out_joint, const float* norm_paths, int32_t T, double circle_var,
                  uint8_t* flags, float* radial_var, uint32_t* keep, void* stream);
 
+/* Bidirectional chamfer distance between paths ("A Case Study of Mechanism
+ * Retrieval"): for two paths A and B of T points each,
+ *   CD(A, B) = mean_a min_b |a - b| + mean_b min_a |a - b|   (Euclidean norm),
+ * computed in FP32 from exact coordinate differences.  A path with a NaN
+ * coordinate has CD = NaN against everything.
+ *   bank    [P][T][2] float  normalised paths (DIAMETER mode in the paper)
+ *   queries [Q][T][2] float  normalised target paths
+ *   dist    [Q][P]    float  CD of every (query, bank path) pair
+ * Errors: LINKS_ERR_ARG for P < 0, Q < 0, T outside [1, 256], or a NULL array
+ * when P and Q are both > 0.  Asynchronous on `stream`. */
+int links_chamfer(links_ctx* ctx, const float* bank, int32_t P, int32_t T, const float* queries, int32_t Q,
+                  float* dist, void* stream);
+
+/* Path retrieval over a bank ("A Case Study of Mechanism Retrieval": a bank path
+ * matches a query when its CD is below a cut-off, 0.03 in the paper).
+ *   LINKS_SEARCH_FIRST  go through the bank in order (the paper shuffles the
+ *                       curated set first: pass it shuffled) until k matches are
+ *                       found: the k lowest bank positions with CD < cutoff;
+ *                       the scan stops early once every query has k matches
+ *   LINKS_SEARCH_BEST   the k smallest CDs below cutoff over the whole bank,
+ *                       equal CDs in bank order (cutoff = INFINITY: plain top k)
+ * Outputs (device): idx [Q][k] int64 bank positions (-1 where fewer than k
+ * matches exist) and dist [Q][k] float their CD (NaN where idx is -1).  The
+ * call returns when the search has finished (it synchronises `stream`: the
+ * FIRST scan decides on the host when to stop).  Errors: those of
+ * links_chamfer, k outside [1, 16], a NaN cutoff or a bad order. */
+#define LINKS_SEARCH_FIRST 0
+#define LINKS_SEARCH_BEST 1
+int links_chamfer_search(links_ctx* ctx, const float* bank, int32_t P, int32_t T, const float* queries,
+                         int32_t Q, int32_t k, float cutoff, int32_t order, int64_t* idx, float* dist,
+                         void* stream);
+
 /* Replayable launch sequence.  links_graph_create records the passes of one
  * links_simulate call with exactly these arguments into a HIP graph (captured on
  * a private stream; nothing runs yet) and returns it in *graph.  Every replay by

@@ -2,6 +2,7 @@
 // workspace management, the crank table and the launch sequence of one call.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -89,6 +90,9 @@ struct links_ctx {
   // held by live graphs is never reallocated
   bool capturing = false;
   int graphs = 0;
+  // pinned host copy of the running retrieval result (FIRST scans)
+  uint64_t* hkeys = nullptr;
+  size_t hkeys_bytes = 0;
 };
 
 struct links_graph {
@@ -229,6 +233,7 @@ void links_destroy(links_ctx* ctx) {
     if (e) (void)hipEventDestroy(e);
   for (auto& kv : ctx->bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
+  if (ctx->hkeys) (void)hipHostFree(ctx->hkeys);
   delete ctx;
 }
 
@@ -841,6 +846,127 @@ int links_normalize_paths_n(links_ctx* ctx, const float* paths, const int32_t* c
   int rc = set_device(ctx);
   if (rc) return rc;
   HIP_CHECK(links::launch_normalize(paths, cap, count, T, mode, out, xform, (hipStream_t)stream));
+  return LINKS_OK;
+}
+
+
+namespace {
+
+int check_chamfer(const float* bank, int32_t P, int32_t T, const float* queries, int32_t Q) {
+  if (P < 0) return fail(LINKS_ERR_ARG, "P = %d < 0", P);
+  if (Q < 0) return fail(LINKS_ERR_ARG, "Q = %d < 0", Q);
+  if (T < 1 || T > links::kChamferMaxT) return fail(LINKS_ERR_ARG, "T = %d outside [1, %d]", T, links::kChamferMaxT);
+  if (P > 0 && Q > 0 && (!bank || !queries)) return fail(LINKS_ERR_ARG, "NULL array");
+  return LINKS_OK;
+}
+
+// waves per query: twice the resident waves of the chip over all queries, at
+// most one per bank path
+int32_t chamfer_waves(links_ctx* ctx, int32_t T, int64_t Q, int64_t P) {
+  const std::string key = "chamfer" + std::to_string(links::chamfer_na(T));
+  auto it = ctx->occ_cache.find(key);
+  if (it == ctx->occ_cache.end()) it = ctx->occ_cache.emplace(key, links::chamfer_blocks_per_cu(T)).first;
+  const int64_t resident = (int64_t)ctx->num_cu * it->second * 4;
+  int64_t w = (2 * resident + Q - 1) / std::max<int64_t>(Q, 1);
+  w = std::min<int64_t>(w, std::max<int64_t>(P, 1));
+  return (int32_t)std::max<int64_t>(1, std::min<int64_t>(w, 1 << 20));
+}
+
+}  // namespace
+
+int links_chamfer(links_ctx* ctx, const float* bank, int32_t P, int32_t T, const float* queries, int32_t Q,
+                  float* dist, void* stream) {
+  if (!ctx) return fail(LINKS_ERR_ARG, "ctx is NULL");
+  int rc = check_chamfer(bank, P, T, queries, Q);
+  if (rc) return rc;
+  if (P == 0 || Q == 0) return LINKS_OK;
+  if (!dist) return fail(LINKS_ERR_ARG, "dist is NULL");
+  rc = set_device(ctx);
+  if (rc) return rc;
+  links::ChamferArgs a{};
+  a.bank = reinterpret_cast<const float2*>(bank);
+  a.P = P;
+  a.T = T;
+  a.queries = reinterpret_cast<const float2*>(queries);
+  a.Q = Q;
+  a.p_lo = 0;
+  a.p_hi = P;
+  a.waves_per_query = chamfer_waves(ctx, T, Q, P);
+  a.dist = dist;
+  HIP_CHECK(links::launch_chamfer(a, (hipStream_t)stream));
+  return LINKS_OK;
+}
+
+int links_chamfer_search(links_ctx* ctx, const float* bank, int32_t P, int32_t T, const float* queries,
+                         int32_t Q, int32_t k, float cutoff, int32_t order, int64_t* idx, float* dist,
+                         void* stream) {
+  if (!ctx) return fail(LINKS_ERR_ARG, "ctx is NULL");
+  int rc = check_chamfer(bank, P, T, queries, Q);
+  if (rc) return rc;
+  if (k < 1 || k > links::kChamferKeep) return fail(LINKS_ERR_ARG, "k = %d outside [1, %d]", k, links::kChamferKeep);
+  if (cutoff != cutoff) return fail(LINKS_ERR_ARG, "cutoff is NaN");
+  if (order != LINKS_SEARCH_FIRST && order != LINKS_SEARCH_BEST) return fail(LINKS_ERR_ARG, "bad order %d", order);
+  if (Q == 0) return LINKS_OK;
+  if (!idx || !dist) return fail(LINKS_ERR_ARG, "NULL output array");
+  rc = set_device(ctx);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  links::ChamferArgs a{};
+  a.bank = reinterpret_cast<const float2*>(bank);
+  a.P = P;
+  a.T = T;
+  a.queries = reinterpret_cast<const float2*>(queries);
+  a.Q = Q;
+  a.k = k;
+  a.cutoff = cutoff;
+  a.order = order == LINKS_SEARCH_FIRST ? links::kChamferFirst : links::kChamferBest;
+  a.waves_per_query = P > 0 ? chamfer_waves(ctx, T, Q, P) : 0;
+  const size_t nrun = (size_t)Q * links::kChamferKeep;
+  void *part = nullptr, *running = nullptr;
+  rc = ensure(ctx, "chamfer_part", std::max<size_t>(1, nrun * a.waves_per_query) * sizeof(uint64_t), &part);
+  if (rc) return rc;
+  rc = ensure(ctx, "chamfer_run", nrun * sizeof(uint64_t), &running);
+  if (rc) return rc;
+  a.part = static_cast<uint64_t*>(part);
+  a.running = static_cast<const uint64_t*>(running);
+  uint64_t* run = static_cast<uint64_t*>(running);
+  HIP_CHECK(links::launch_chamfer_clear(run, (int64_t)nrun, st));
+  if (a.order == links::kChamferBest || P == 0) {
+    a.p_lo = 0;
+    a.p_hi = P;
+    HIP_CHECK(links::launch_chamfer(a, st));
+    HIP_CHECK(links::launch_chamfer_merge(a, run, idx, dist, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    return LINKS_OK;
+  }
+  // FIRST: chunks in bank order, growing geometrically; after each, the host
+  // reads the running result and stops once every query holds k matches
+  if (ctx->hkeys_bytes < nrun * sizeof(uint64_t)) {
+    if (ctx->hkeys) (void)hipHostFree(ctx->hkeys);
+    ctx->hkeys = nullptr;
+    ctx->hkeys_bytes = 0;
+    void* h = nullptr;
+    if (hipHostMalloc(&h, nrun * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
+      return fail(LINKS_ERR_OOM, "hipHostMalloc(%zu) failed", nrun * sizeof(uint64_t));
+    ctx->hkeys = static_cast<uint64_t*>(h);
+    ctx->hkeys_bytes = nrun * sizeof(uint64_t);
+  }
+  int64_t chunk = (int64_t)a.waves_per_query * 8;
+  for (int64_t lo = 0; lo < P;) {
+    a.p_lo = lo;
+    a.p_hi = std::min<int64_t>(P, lo + chunk);
+    HIP_CHECK(links::launch_chamfer(a, st));
+    HIP_CHECK(links::launch_chamfer_merge(a, run, idx, dist, st));
+    lo = a.p_hi;
+    if (lo >= P) break;
+    HIP_CHECK(hipMemcpyAsync(ctx->hkeys, run, nrun * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    bool all = true;
+    for (int32_t q = 0; q < Q && all; q++) all = ctx->hkeys[(size_t)q * links::kChamferKeep + k - 1] != ~0ull;
+    if (all) break;
+    chunk = std::min<int64_t>(chunk * 2, (int64_t)a.waves_per_query * 1024);
+  }
+  HIP_CHECK(hipStreamSynchronize(st));
   return LINKS_OK;
 }
 

@@ -139,4 +139,33 @@ int sim64_par_blocks_per_cu(int J, int source, bool exact, int waves, int seg);
 hipError_t launch_normalize(const float* paths, int32_t P, const int32_t* count, int32_t T, int32_t mode,
                             float* out, float* xform, hipStream_t st);
 
+// Bidirectional chamfer distance and retrieval (chamfer.hip).
+constexpr int kChamferKeep = 16;  // largest k of a search
+constexpr int kChamferFirst = 0;  // k lowest bank positions under the cut-off
+constexpr int kChamferBest = 1;   // k smallest distances under the cut-off
+constexpr int kChamferMaxT = 256;
+
+struct ChamferArgs {
+  const float2* bank;     // [P][T]
+  int64_t P;
+  int32_t T;
+  const float2* queries;  // [Q][T]
+  int64_t Q;
+  int64_t p_lo, p_hi;     // bank rows of this launch
+  int32_t waves_per_query;
+  float* dist;            // [Q][P] or null
+  int32_t k;              // 0: no selection
+  float cutoff;
+  int32_t order;
+  uint64_t* part;         // [Q][waves_per_query][kChamferKeep] per-wave lists
+  const uint64_t* running;  // [Q][kChamferKeep] result of earlier launches (FIRST: a full one ends the scan)
+};
+
+int chamfer_na(int T);
+int chamfer_blocks_per_cu(int T);
+hipError_t launch_chamfer(const ChamferArgs& a, hipStream_t st);
+hipError_t launch_chamfer_merge(const ChamferArgs& a, uint64_t* running, int64_t* idx, float* dist,
+                                hipStream_t st);
+hipError_t launch_chamfer_clear(uint64_t* running, int64_t n, hipStream_t st);
+
 }  // namespace links

@@ -340,3 +340,35 @@ def workload(name: str, B: Optional[int] = None, seed: Optional[int] = None, fir
         return standardize_paper(dyad_batch(B or 100_000, 6 if seed is None else seed, n_uniform(8, 20),
                                             20, paper_mode=True, first=first))
     raise KeyError(name)
+
+
+def closed_curves(P: int, T: int, seed: int, harmonics: int = 5) -> np.ndarray:
+    """P closed curves of T points each, float32 [P,T,2], sampled at equally
+    spaced parameter values: random Fourier series with amplitudes falling as
+    1/k^1.5 around a centre near (0.5, 0.5), so that the curves span about a unit
+    box like paths in the paper's normalised frame (synthetic stand-ins for a
+    bank of normalised coupler paths)."""
+    rng = np.random.default_rng(seed)
+    th = 2.0 * np.pi * np.arange(T) / T
+    k = np.arange(1, harmonics + 1)
+    amp = 0.25 / k ** 1.5
+    c = rng.normal(size=(P, 4, harmonics)) * amp                    # cos x, sin x, cos y, sin y
+    cos_kt, sin_kt = np.cos(np.outer(k, th)), np.sin(np.outer(k, th))  # [H, T]
+    x = c[:, 0] @ cos_kt + c[:, 1] @ sin_kt
+    y = c[:, 2] @ cos_kt + c[:, 3] @ sin_kt
+    centre = 0.5 + 0.05 * rng.normal(size=(P, 2))
+    return np.stack([x + centre[:, :1], y + centre[:, 1:]], axis=-1).astype(np.float32)
+
+
+def near_copies(base: np.ndarray, n: int, sigma: float, seed: int) -> np.ndarray:
+    """n noisy copies of each curve of base [P,T,2]: every point moved by
+    N(0, sigma^2) per coordinate and the point order rotated by a random shift
+    (the same path started elsewhere) -> float32 [P*n,T,2]."""
+    rng = np.random.default_rng(seed)
+    P, T = base.shape[0], base.shape[1]
+    out = np.repeat(base.astype(np.float64), n, axis=0)
+    shift = rng.integers(0, T, size=P * n)
+    rows = (np.arange(T)[None, :] + shift[:, None]) % T
+    out = np.take_along_axis(out, rows[:, :, None], axis=1)
+    out += rng.normal(scale=sigma, size=out.shape)
+    return out.astype(np.float32)

@@ -27,6 +27,7 @@ F32, F64 = 0, 1
 NORM_PCA, NORM_DIAMETER = 0, 1
 NF_CONSTANT, NF_ISOTROPIC, NF_SIGN_TIE, NF_DIAM_TIE = 1, 2, 4, 8
 CURATE_ARC, CURATE_CIRCLE = 1, 2
+SEARCH_FIRST, SEARCH_BEST = 0, 1
 
 P = ctypes.c_void_p
 i32 = ctypes.c_int32
@@ -93,6 +94,10 @@ def load() -> ctypes.CDLL:
     L.links_get_option.restype = ctypes.c_int
     L.links_normalize_paths_n.argtypes = [P, P, P, i32, i32, i32, P, P, P]
     L.links_normalize_paths_n.restype = ctypes.c_int
+    L.links_chamfer.argtypes = [P, P, i32, i32, P, i32, P, P]
+    L.links_chamfer.restype = ctypes.c_int
+    L.links_chamfer_search.argtypes = [P, P, i32, i32, P, i32, i32, ctypes.c_float, i32, P, P, P]
+    L.links_chamfer_search.restype = ctypes.c_int
     L.links_profile.argtypes = [P, ctypes.c_int]
     L.links_profile.restype = ctypes.c_int
     L.links_last_timings.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
@@ -128,6 +133,12 @@ def _ptr(t: Optional[torch.Tensor]):
     if not t.is_cuda or not t.is_contiguous():
         raise ValueError("expected a contiguous device tensor")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _paths_arg(t: torch.Tensor, name: str) -> torch.Tensor:
+    if t.dtype != torch.float32 or t.dim() != 3 or t.shape[2] != 2:
+        raise ValueError(f"{name} must be a float32 [n, T, 2] tensor")
+    return t
 
 
 def _stream(stream=None):
@@ -343,6 +354,32 @@ class Context:
                                               _stream(stream)), "links_normalize_paths_n")
         return out, xform
 
+
+    def chamfer(self, bank: torch.Tensor, queries: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None):
+        """Bidirectional chamfer distance of every query [Q,T,2] against every bank
+        path [P,T,2] (float32, on the device) -> [Q,P] float32."""
+        bank, queries = _paths_arg(bank, "bank"), _paths_arg(queries, "queries")
+        Pn, T, Q = int(bank.shape[0]), int(bank.shape[1]), int(queries.shape[0])
+        if int(queries.shape[1]) != T:
+            raise ValueError("bank and queries need the same number of points")
+        out = torch.empty((Q, Pn), dtype=torch.float32, device=bank.device) if out is None else out
+        _check(load().links_chamfer(self._h, _ptr(bank), Pn, T, _ptr(queries), Q, _ptr(out), _stream(stream)),
+               "links_chamfer")
+        return out
+
+    def chamfer_search(self, bank: torch.Tensor, queries: torch.Tensor, k: int = 3, cutoff: float = 0.03,
+                       order: int = SEARCH_FIRST, stream=None):
+        """Retrieval of k bank paths per query (see links_chamfer_search) ->
+        (idx [Q,k] int64, dist [Q,k] float32); returns once the search is done."""
+        bank, queries = _paths_arg(bank, "bank"), _paths_arg(queries, "queries")
+        Pn, T, Q = int(bank.shape[0]), int(bank.shape[1]), int(queries.shape[0])
+        if int(queries.shape[1]) != T:
+            raise ValueError("bank and queries need the same number of points")
+        idx = torch.empty((Q, k), dtype=torch.int64, device=bank.device)
+        dist = torch.empty((Q, k), dtype=torch.float32, device=bank.device)
+        _check(load().links_chamfer_search(self._h, _ptr(bank), Pn, T, _ptr(queries), Q, k, float(cutoff), order,
+                                           _ptr(idx), _ptr(dist), _stream(stream)), "links_chamfer_search")
+        return idx, dist
 
 class Graph:
     """A recorded links_simulate launch sequence (see links_graph_create)."""
