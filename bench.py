@@ -466,6 +466,7 @@ def retrieval_config(args, L, gen):
     xf = torch.empty((cap, 5), dtype=torch.float32, device=dev)
 
     norm = torch.empty((cap, T, 2), dtype=torch.float32, device=dev)
+    shapes = {"valid": 0, "arc": 0, "circle": 0, "either": 0}
 
     def valid_paths(seed, n_cand, first, out_rows, lo):
         """Curated paths of one chunk: valid, DIAMETER-normalised, circles and arcs
@@ -477,6 +478,11 @@ def retrieval_config(args, L, gen):
             return 0
         ctx.normalize_paths(r["path"][:n], L.NORM_DIAMETER, out=norm[:n], xform=xf[:n])
         fl = ctx.curate(b, norm[:n], path_index=r["path_index"][:n])["flags"]
+        if seed == 7:
+            shapes["valid"] += n
+            shapes["arc"] += int(((fl & L.CURATE_ARC) != 0).sum())
+            shapes["circle"] += int(((fl & L.CURATE_CIRCLE) != 0).sum())
+            shapes["either"] += int((fl != 0).sum())
         keep = norm[:n][fl == 0]
         m = min(int(keep.shape[0]), out_rows.shape[0] - lo)
         out_rows[lo:lo + m] = keep[:m]
@@ -545,7 +551,11 @@ def retrieval_config(args, L, gen):
             "oracle_check": {"rows_checked": checked, "max_rel_err": max(errs)},
             "cpu_baseline": {"value": cpu_rate, "unit": "comparisons/s", "cores": 1, "kind": "oracle",
                              "sample": f"1 query against {cpu_n} bank paths (numpy float64)"},
-            "bank_build_s": build_s}
+            "bank_build_s": build_s,
+            "path_shapes": {"valid_paths_seen": shapes["valid"],
+                            "arc_fraction": shapes["arc"] / max(shapes["valid"], 1),
+                            "circle_fraction": shapes["circle"] / max(shapes["valid"], 1),
+                            "arc_or_circle_fraction": shapes["either"] / max(shapes["valid"], 1)}}
 
 
 def main():
