@@ -951,7 +951,7 @@ int links_chamfer_search(links_ctx* ctx, const float* bank, int32_t P, int32_t T
     ctx->hkeys = static_cast<uint64_t*>(h);
     ctx->hkeys_bytes = nrun * sizeof(uint64_t);
   }
-  int64_t chunk = (int64_t)a.waves_per_query * 8;
+  int64_t chunk = (int64_t)a.waves_per_query * 2;
   for (int64_t lo = 0; lo < P;) {
     a.p_lo = lo;
     a.p_hi = std::min<int64_t>(P, lo + chunk);
