@@ -62,6 +62,11 @@ sim32_kernel(SimArgs A) {
   float px = 0.f, py = 0.f, vx = 0.f, vy = 0.f, U = 0.f, KB = 0.f, CD = 0.f, EB = 0.f;
   float U2 = 0.f, TS = 0.f, uu = 0.f, DG = 0.f;
   bool force64 = false;
+  // A finished candidate's results are written later, for all finished lanes of
+  // the wave together (at the next refill or when the wave leaves): its lane is
+  // idle meanwhile and keeps its slots in LDS for the hand-over dump.
+  int fin = 0;  // 0 nothing pending, 1 locked or degenerate, 2 handed over, 3 valid
+  int fcand = 0, fkind = 0, fstep = 0;
   const bool orient = A.branch != 0;  // sides fixed at the start (else continuity)
   uint32_t obits = 0u;                // starting side of each placed joint
   int dmax_w = 0;  // largest solve order among the wave's lanes (uniform)
@@ -133,12 +138,47 @@ sim32_kernel(SimArgs A) {
     return false;
   };
 
+  // results of the finished lanes: one store per result, one atomic for the
+  // wave's hand-overs (each lane's queue entry at base + its rank), and the
+  // positions of the handed-over candidates at their sorted-position rows
+  auto flush = [&]() {
+    if (__ballot(fin != 0) == 0ull) return;
+    if (fin == 1 || fin == 3) {
+      A.status[fcand] = (uint8_t)(fin == 3 ? 0 : fkind);
+      A.fail_step[fcand] = (int16_t)(fin == 3 ? -1 : fstep);
+      if (A.esc_step && !A.resume) A.esc_step[fcand] = -1;
+    }
+    const uint64_t em = __ballot(fin == 2);
+    if (em != 0ull) {
+      const int leader = __ffsll((unsigned long long)em) - 1;
+      int base = 0;
+      if (lane_id() == leader) base = atomicAdd(&A.counters[kCntEsc], __popcll(em));
+      base = __shfl(base, leader);
+      if (fin == 2) {
+        EscEntry e;
+        e.item = item;
+        e.t = (int16_t)fstep;
+        e.from_x0 = force64 ? 1 : 0;
+        e.pad = 0;
+        A.esc[base + mbcnt64(em)] = e;
+        float2* dump = A.esc_pos + (size_t)item * J;  // the candidate's own row
+        for (int sl = 0; sl < n; ++sl) dump[sl] = P[sl * bd + tid];
+        if (A.esc_step && !A.resume) A.esc_step[fcand] = (int16_t)fstep;  // the first hand-over
+      }
+    }
+    fin = 0;
+  };
+
   for (;;) {
     // ---------------- refill idle lanes (wave-uniform control flow)
     uint64_t idle = __ballot(cand < 0);
     int nidle = __popcll(idle);
-    if (nidle == kWave && exhausted) break;
+    if (nidle == kWave && exhausted) {
+      flush();
+      break;
+    }
     if (!exhausted && nidle > 0 && (nidle >= rm || nidle == kWave)) {
+      flush();  // before new candidates take the finished lanes' slots
       int p = -1;
       // hand out the wave's claimed ranges: the current one, then the next one
       // (resolving the claim made ahead when the current range cannot cover)
@@ -360,30 +400,18 @@ sim32_kernel(SimArgs A) {
 
     bool done = false;
     if (ev) {
-      if (lock_ev) {
-        A.status[cand] = (uint8_t)lock_kind;
-        A.fail_step[cand] = (int16_t)t;
-        if (A.esc_step && !A.resume) A.esc_step[cand] = -1;
-      } else {
-        int i = atomicAdd(&A.counters[kCntEsc], 1);
-        EscEntry e;
-        e.item = item;
-        e.t = (int16_t)t;
-        e.from_x0 = force64 ? 1 : 0;
-        e.pad = 0;
-        A.esc[i] = e;
-        float2* dump = A.esc_pos + (size_t)item * J;  // the candidate's own row
-        for (int sl = 0; sl < n; ++sl) dump[sl] = P[sl * bd + tid];
-        if (A.esc_step && !A.resume) A.esc_step[cand] = (int16_t)t;  // the first hand-over
-      }
+      fin = lock_ev ? 1 : 2;
+      fkind = lock_kind;
+      fstep = t;
       done = true;
     } else if (++t == T) {
-      A.status[cand] = 0;
-      A.fail_step[cand] = -1;
-      if (A.esc_step && !A.resume) A.esc_step[cand] = -1;
+      fin = 3;
       done = true;
     }
-    if (done) cand = -1;
+    if (done) {
+      fcand = cand;
+      cand = -1;
+    }
     }
   }
 }
