@@ -461,7 +461,16 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   int32_t* block_hist;
   int32_t* block_off;
   int32_t* scratch;
+  uint32_t* side_ck = nullptr;
   const size_t nblocks = (size_t)prep_blocks(B);
+  // FP64 precision: path rows in chunks of kPathChunk steps, each on a lane of
+  // its own, starting from the sides the step-by-step FP64 pass records at the
+  // chunk boundaries.  (With FP32 decisions recording the sides costs the FP32
+  // pass about what the path pass gains, so those rows are computed whole.)
+  const int ck_n = (T + kPathChunk - 1) / kPathChunk;
+  const bool chunks = opts->precision == LINKS_FP64 && opts->write != LINKS_WRITE_NONE &&
+                      !(opts->write == LINKS_WRITE_VALID && out->cap == 0) && ck_n > 1 && ctx->par64 != 2;
+  if (chunks && (rc = ensure_t(ctx, "side_ck", (size_t)B * ck_n, &side_ck))) return rc;
   if ((rc = ensure_t(ctx, "meta", B, &meta)) || (rc = ensure_t(ctx, "cf", B, &cf)) ||
       (rc = ensure_t(ctx, "cd", B, &cd)) || (rc = ensure_t(ctx, "df", (size_t)B * J, &df)) ||
       (rc = ensure_t(ctx, "dd", (size_t)B * J, &dd)) || (rc = ensure_t(ctx, "x0s", (size_t)B * J, &x0s)) ||
@@ -577,6 +586,8 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   sa.resume = 0;
   sa.chunk = ctx->chunk;
   sa.branch = opts->branch;
+  sa.side_ck = side_ck;
+  sa.ck_n = chunks ? ck_n : 1;
 
   LaunchCfg c64;
   c64.waves = ctx->waves64;

@@ -73,6 +73,10 @@ struct EscEntry {
   int8_t pad;
 };
 
+// steps per chunk of a path row (a power of two, and a multiple of the 8- and
+// 4-step write groups of the path pass)
+constexpr int kPathChunk = 32;
+
 // Pointers of the workspace and of the caller's batch, passed by value to kernels.
 struct SimArgs {
   // batch
@@ -114,6 +118,13 @@ struct SimArgs {
   int32_t spread;      // FP32 pass: waves start spread over the buckets (1) or all in the largest (0)
   int32_t chunk;       // items a wave claims with one atomic
   int32_t branch;      // LINKS_BRANCH_CONTINUITY or LINKS_BRANCH_ORIENTATION (side bits of the records)
+  // Side bits of every placed joint (bit s: dyad s on the left of its parents'
+  // line) after step k * kPathChunk - 1, k = 1 .. ck_n - 1, by candidate
+  // ([B][ck_n], entry 0 unused): written by the step-by-step FP64 decision pass,
+  // read by the path pass, which then computes each chunk of kPathChunk steps of
+  // a row on its own lane (null: rows computed whole).
+  uint32_t* side_ck;
+  int32_t ck_n;
   // returning to FP32 after a hand-over: the FP64 pass stops a candidate deesc
   // steps after its hand-over step and queues it (res, res_pos); a resume round of
   // the FP32 pass (resume = 1) takes its work items from that queue

@@ -111,6 +111,18 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
   uint32_t obits = 0u;                // starting side of each placed joint
   double px = 0, py = 0, vx = 0, vy = 0, deg_thr = 0, drift_thr = 0;
   bool exhausted = false;
+  // Path chunks: a path-pass work item is one chunk of ck_len steps of a row; a
+  // chunk after the first starts with the step before it, placed on the sides the
+  // decision passes recorded there (forced) and not written.  The decision passes
+  // record sb, the sides of the current step, every ck_len steps.
+  // (compiled into the FP64-precision instantiations only: the exact arithmetic's
+  // step-by-step decision pass records, its path pass reads)
+  constexpr bool REC = SRC == kFromPerm && EXACT;
+  constexpr bool CK = SRC == kFromPath && EXACT;
+  const bool chunked = CK && A.side_ck != nullptr;
+  const int ckn = chunked ? A.ck_n : 1;
+  uint32_t sb = 0u, fbits = 0u;
+  bool forced = false;
   // per-entry constants of the lane's candidate, held in registers: S, Dm and
   // ra^2, rb^2 (EXACT) or Kc = (ra^2 - rb^2)/2 (fast)
   double cS[DMAX], cDm[DMAX], cA[DMAX], cB[DMAX];
@@ -136,7 +148,7 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
     if (nidle == kWave && exhausted) break;
     // idle lanes wait until enough of them can be refilled
     if (!exhausted && nidle > 0 && (nidle >= A.refill_min || nidle == kWave)) {
-      const int items = A.counters[cnt_items];
+      const int items = A.counters[cnt_items] * ckn;
       int p = -1;
       for (int k = 0; k < 3 && nidle > 0; ++k) {
         if (cur_left == 0) {
@@ -179,7 +191,7 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
             t0 = e.t;
             from_x0 = e.from_x0 != 0;
           } else if (SRC == kFromPath) {
-            it = A.path_list[p];
+            it = A.path_list[chunked ? p / ckn : p];
           } else {
             it = p;
           }
@@ -193,7 +205,21 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
             row = A.write_all ? (int64_t)c : (int64_t)A.path_row[c];
             const int fs = A.fail_step[c];
             if (fs >= 0) t_end = fs;  // the path exists up to the failing step
-            take = row >= 0 && t_end > 0;
+            forced = false;
+            if (chunked) {
+              const int kc = p % ckn, t0c = kc * kPathChunk;
+              t_end = min(t_end, t0c + kPathChunk);
+              if (kc > 0) {
+                if (t0c < t_end) {
+                  forced = true;
+                  fbits = A.side_ck[(size_t)c * ckn + kc];
+                  t = t0c - 1;
+                } else {
+                  t_end = 0;  // the row ends before this chunk
+                }
+              }
+            }
+            take = row >= 0 && t < t_end && t_end > 0;
           }
           if (take) {
             const CandMeta m = A.meta[it];
@@ -284,6 +310,7 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
       else
         P[D * bd + tid] = make_double2(fma(ct, vx, fma(-st, vy, px)), fma(st, vx, fma(ct, vy, py)));
       int fail = 0;
+      sb = 0u;
 #pragma unroll
       for (int s = 0; s < DMAX; ++s) {
         if (s < D && fail == 0) {
@@ -314,7 +341,8 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
                 const double cmx = bx - ox, cmy = by - oy;
                 const double dp2 = (pr.x - cpx) * (pr.x - cpx) + (pr.y - cpy) * (pr.y - cpy);
                 const double dm2 = (pr.x - cmx) * (pr.x - cmx) + (pr.y - cmy) * (pr.y - cmy);
-                const bool left = orient ? ((obits >> s) & 1u) != 0u : dp2 <= dm2;
+                const bool left = (orient || forced) ? (((forced ? fbits : obits) >> s) & 1u) != 0u : dp2 <= dm2;
+                if (REC) sb |= (left ? 1u : 0u) << s;
                 P[s * bd + tid] = left ? make_double2(cpx, cpy) : make_double2(cmx, cmy);
               }
             }
@@ -343,8 +371,26 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
         }
       }
       if (fail == 0 && redundant && drift_check(A, cand, item, D, n, P, bd, tid, drift_thr)) fail = 3;
+      if (REC && A.side_ck != nullptr && fail == 0 && t + 1 < T && ((t + 1) & (kPathChunk - 1)) == 0)
+        A.side_ck[(size_t)cand * A.ck_n + (t + 1) / kPathChunk] = sb;
       bool done = false;
-      if (SRC == kFromPath && DMAX > 5) {
+      if (CK && forced) {
+        // the step before the chunk: its positions only
+        forced = false;
+        if (fail != 0) {
+          // (possible only within rounding of a threshold) the chunk's row stays NaN
+          const double nan = __builtin_nan("");
+          for (int tt = t + 1; tt < t_end; ++tt) {
+            if (A.path_f64)
+              reinterpret_cast<double2*>(A.path)[row * T + tt] = make_double2(nan, nan);
+            else
+              reinterpret_cast<float2*>(A.path)[row * T + tt] = make_float2((float)nan, (float)nan);
+          }
+          done = true;
+        } else {
+          ++t;
+        }
+      } else if (SRC == kFromPath && DMAX > 5) {
         double2 po = P[out_slot * bd + tid];
         if (fail != 0) po = make_double2(__builtin_nan(""), __builtin_nan(""));
         const int t_stop = fail != 0 ? t_end : t + 1;
