@@ -14,7 +14,7 @@
 // bank point) over u.  Indices past T - 1 repeat point T - 1: a repeated point
 // leaves every minimum unchanged and is left out of the sums.
 //
-// Selection keeps, per wave, the kKeep smallest 64-bit keys of the paths under
+// Selection keeps, per wave, the kChamferKeep smallest 64-bit keys of the paths under
 // the cut-off (FIRST: position then distance bits; BEST: distance bits then
 // position -- distances are >= 0, so their bit patterns order like the values);
 // a merge kernel combines the waves' lists with the result of earlier launches.
@@ -173,7 +173,7 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int m) {
   return (uint64_t)hi << 32 | lo;
 }
 
-// One workgroup per query: the kKeep smallest keys among the waves' lists and
+// One workgroup per query: the kChamferKeep smallest keys among the waves' lists and
 // the running result, written back to the running result and to idx / dist.
 __global__ __launch_bounds__(256) void chamfer_merge_kernel(ChamferArgs A, uint64_t* running, int64_t* idx,
                                                             float* dist) {
