@@ -66,3 +66,28 @@ def test_fourbar_rejection_gives_grashof_crank_rockers():
     allL = np.stack([crank, coupler, rocker, ground], 1)
     s, l = allL.min(1), allL.max(1)
     assert np.all(crank == s) and np.all(s + l < allL.sum(1) - s - l)
+
+
+def test_closed_curves_are_seeded_and_closed():
+    a = gen.closed_curves(50, 64, seed=3)
+    b = gen.closed_curves(50, 64, seed=3)
+    c = gen.closed_curves(50, 64, seed=4)
+    assert a.shape == (50, 64, 2) and a.dtype == np.float32
+    assert np.array_equal(a, b) and not np.array_equal(a, c)
+    assert np.isfinite(a).all()
+    # a Fourier series without a constant term: the points average to the centre,
+    # which lies near (0.5, 0.5)
+    centre = a.astype(np.float64).mean(axis=1)
+    assert np.all(np.abs(centre - 0.5) < 0.3)
+
+
+def test_near_copies_shift_the_start_and_add_noise():
+    base = gen.closed_curves(4, 40, seed=8)
+    near = gen.near_copies(base, 3, 0.0, seed=9)
+    assert near.shape == (12, 40, 2)
+    for i in range(12):
+        # without noise each copy is its curve with the start point moved
+        src = base[i // 3]
+        assert any(np.array_equal(near[i], np.roll(src, -k, axis=0)) for k in range(40))
+    noisy = gen.near_copies(base, 2, 0.01, seed=9)
+    assert not np.array_equal(noisy, gen.near_copies(base, 2, 0.0, seed=9))
