@@ -43,7 +43,7 @@ def _sides_and_mirror_gap(b, r, order, nd, c, T):
 
 def test_rules_keep_their_invariants():
     T = 60
-    b = gen.dyad_batch(200, 17, gen.n_uniform(5, 9), J=10)
+    b = gen.dyad_batch(400, 17, gen.n_uniform(5, 9), J=10)
     order, nd, _, _ = oracle.solve_order(b)
     rc = oracle.simulate(b, T=T, pos_all=True)
     ro = oracle.simulate(b, T=T, pos_all=True, branch=oracle.BRANCH_ORIENTATION)
@@ -75,7 +75,7 @@ def test_rules_agree_where_continuity_keeps_the_starting_sides():
     qualify; a coupler point almost on its parents' line may change side under
     continuity)."""
     T = 200
-    b = gen.workload("fourbar", 300, seed=9)
+    b = gen.workload("fourbar", 600, seed=9)
     order, nd, _, _ = oracle.solve_order(b)
     rc = oracle.simulate(b, T=T, path=True, pos_all=True)
     ro = oracle.simulate(b, T=T, path=True, branch=oracle.BRANCH_ORIENTATION)

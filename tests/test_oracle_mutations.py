@@ -13,6 +13,7 @@ from tests import test_oracle_fourbar as fb
 from tests import test_oracle_curate as cu
 from tests import test_oracle_order as od
 from tests import test_oracle_branch as br
+from tests import test_oracle_margins as mg
 
 MUTATIONS = {
     "offset_sign": ("double ox = -(h / d) * dy;", "double ox = (h / d) * dy;"),
@@ -38,6 +39,21 @@ MUTATIONS = {
     "ancestors_forward": ("for (int s = nd - 1; s >= 0; s--) {\n      int k = order[3 * s];",
                           "for (int s = 0; s < nd; s++) {\n      int k = order[3 * s];"),
     "arc_any_link": ("if (a[out] & fixed[c]) f |= LREF_CUR_ARC;", "if (a[out]) f |= LREF_CUR_ARC;"),
+    # the band margins that decide which candidates are excused from bit-exact parity
+    "branch_margin_x10": ("if (side / scale < m_branch) m_branch = side / scale;",
+                          "if (10.0 * side / scale < m_branch) m_branch = 10.0 * side / scale;"),
+    "branch_margin_to_base": (
+        "double side = fabs((prev[k][0] - bx) * (-dy) + (prev[k][1] - by) * dx) / d;",
+        "double side = sqrt((prev[k][0] - bx) * (prev[k][0] - bx) + (prev[k][1] - by) * (prev[k][1] - by));"),
+    "branch_margin_not_over_d": ("double side = fabs((prev[k][0] - bx) * (-dy) + (prev[k][1] - by) * dx) / d;",
+                                 "double side = fabs((prev[k][0] - bx) * (-dy) + (prev[k][1] - by) * dx);"),
+    "drift_margin_without_tau": ("double md = fabs(drift - A->tau_drift * scale) / scale;",
+                                 "double md = fabs(drift) / scale;"),
+    "drift_margin_unscaled": ("double md = fabs(drift - A->tau_drift * scale) / scale;",
+                              "double md = fabs(drift - A->tau_drift * scale);"),
+    "disc_margin_unscaled": ("if (fabs(disc) / scale2 < m_disc) m_disc = fabs(disc) / scale2;",
+                             "if (fabs(disc) < m_disc) m_disc = fabs(disc);"),
+    "deg_margin_unscaled": ("if (d2 / scale2 < m_deg) m_deg = d2 / scale2;", "if (d2 < m_deg) m_deg = d2;"),
 }
 
 PINS = [
@@ -53,6 +69,11 @@ PINS = [
     lambda: cu.test_reduced_mechanism_reproduces_the_path(None),
     br.test_rules_keep_their_invariants,
     br.test_rules_agree_where_continuity_keeps_the_starting_sides,
+    lambda: fb.test_discriminant_and_distance_margins_closed_form(None),
+    mg.test_branch_margin_fourbar_closed_form,
+    mg.test_margins_of_a_crank_carried_joint_closed_form,
+    mg.test_drift_margin_of_the_crank_tip_closed_form,
+    mg.test_drift_margin_through_the_rocker_closed_form,
 ]
 
 
