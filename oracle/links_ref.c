@@ -598,6 +598,8 @@ int links_ref_curate(int32_t J, const uint8_t* n, const uint32_t* adj, const uin
     }
     var /= (double)T;
     radial_var[i] = var;
+    /* only a well-formed mechanism that the solver can place is curated */
+    if (!structure_ok(J, n[c], a, fixed[c], pivot, tip)) continue;
     if (!solve_order_one(n[c], a, fixed[c], tip, order, &nd, &dp)) continue;
     int out = out_joint >= 0 ? out_joint : (nd > 0 ? order[3 * (nd - 1)] : tip);
     uint32_t f = 0u;
