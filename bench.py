@@ -27,11 +27,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "mechanism sims/sec (200 steps) FP32+recheck vs FP64 plain; p99 request latency"
 
-# algorithmic floating-point operations, counted from the formulas (add, mul,
-# compare, min/max, sqrt/rsq/div = 1; fma = 2)
-FLOP_DYAD_FP32 = 40   # one placement: d^2, discriminant, 1/d, sqrt K, foot, normal, branch, lock/band tests
-FLOP_TIP = 8          # crank rotation of the tip per step
-FLOP_DYAD_FP64 = 42   # the FP64 step formula (two sqrt, four divisions, both branch distances)
+# algorithmic floating-point operations of the method itself, whatever the
+# precision or the bookkeeping around it (error bounds, bands): one placement is
+# the parents' difference (2), d^2 (3), the foot ratio (2), h^2 (3), the lock and
+# degenerate tests (2), h and h/d (3), the foot (4), the offset (2), the
+# continuity test (4) and the chosen intersection (2): 27, taken as 30; the crank
+# rotation of the tip is 4 fused multiply-adds per step
+FLOP_DYAD = 30
+FLOP_TIP = 8
 # published vector peaks; FP32 = 256 CUs x 128 lanes per clock x 2.4 GHz x 2 (FMA).  The
 # build disables packed FP32, yet the chamfer kernel issues about 76 FP32 lanes per
 # clock per CU (rocprofv3 SQ_INSTS_VALU), above a 64-lane ceiling: the full FP32
@@ -174,15 +177,14 @@ def time_sim(ctx, db, reps, warmup=2, **kw):
         ctx.simulate(db, **kw)
     torch.cuda.synchronize()
     ctx.profile(True)
-    passes = []
     t0 = time.perf_counter()
     for _ in range(reps):
         r = ctx.simulate(db, **kw)
-        passes.append(ctx.last_timings())
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
+    mean = ctx.mean_timings(min(reps, 64))
     ctx.profile(False)
-    return dt, {k: float(np.mean([p[k] for p in passes])) for k in passes[0]}, r
+    return dt, mean, r
 
 
 def stream_config(args, L, gen, oracle, tune, dev, threads):
@@ -634,17 +636,18 @@ def main():
         for _ in range(args.warmup):
             step(c, precision)
         torch.cuda.synchronize()
+        # HIP events around every pass of every timed step, on the library's
+        # stream, read back only after the timed region (no host synchronisation
+        # inside it)
         c.profile(True)
-        passes = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
             step(c, precision)
-            passes.append(c.last_timings())
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        mean = c.mean_timings(min(args.steps, 64))
         c.profile(False)
-        mean = {k: float(np.mean([p[k] for p in passes])) for k in passes[0]}
         log(f"{label}: {dt / args.steps * 1e3:.3f} ms/step, passes (ms): " +
             ", ".join(f"{k} {v:.3f}" for k, v in mean.items()))
         return dt / args.steps, mean
@@ -656,10 +659,12 @@ def main():
     nw = int(out["n_written"].cpu()[0])
     nd = ctx.solve_order(db)[1].cpu().numpy()
     steps32, dsteps32 = executed_work(st, fs, es, nd, T)
-    flop32 = float(dsteps32.sum()) * FLOP_DYAD_FP32 + float(steps32.sum()) * FLOP_TIP
+    flop32 = float(dsteps32.sum()) * FLOP_DYAD + float(steps32.sum()) * FLOP_TIP
     t32 = pass32["fp32_pass"] * 1e-3
     achieved = flop32 / t32
     decided = np.where(st == 0, T, fs.astype(np.int64) + 1)
+    # the whole step: every decided candidate-step once, over the step's wall time
+    step_flop = float((decided * nd).sum()) * FLOP_DYAD + float(decided.sum()) * FLOP_TIP
     stats = {
         "valid_fraction": float((st == 0).mean()),
         "escalated_fraction": float((es >= 0).mean()),
@@ -684,7 +689,7 @@ def main():
         st64 = out["status"].cpu().numpy()
         fs64 = out["fail_step"].cpu().numpy()
         d64 = np.where(st64 == 0, T, np.where(fs64 >= 0, fs64, 0)).astype(np.int64)
-        flop64 = float((d64 * nd).sum()) * FLOP_DYAD_FP64 + float(d64.sum()) * FLOP_TIP
+        flop64 = float((d64 * nd).sum()) * FLOP_DYAD + float(d64.sum()) * FLOP_TIP
         fp64 = {"value": B / sec64, "ms_per_step": sec64 * 1e3, "speedup_fp32_recheck_over_fp64": sec64 / sec32,
                 "fp64_pass_ms": pass64["fp64_pass"], "passes_ms": pass64,
                 "tuning": tuned64["config"] if tuned64 else None,
@@ -796,7 +801,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK, "traffic": traffic_from_profile(),
                      "kernel": "sim32_kernel (FP32 pass)", "kernel_ms": t32 * 1e3,
-                     "flop_per_dyad_step": FLOP_DYAD_FP32, "flop_per_step": FLOP_TIP,
+                     "flop_per_dyad_step": FLOP_DYAD, "flop_per_step": FLOP_TIP,
+                     "step_achieved": step_flop / sec32 / 1e12, "step_frac": step_flop / sec32 / FP32_PEAK,
                      "dyad_steps": int(dsteps32.sum()), "candidate_steps": int(steps32.sum())},
         "cpu_baseline": cpu,
         "fp64_plain": fp64,

@@ -336,17 +336,24 @@ int links_graph_create(links_ctx* ctx, const links_batch* batch, const links_sim
 int links_graph_launch(links_graph* graph, void* stream);
 void links_graph_destroy(links_graph* graph);
 
-/* Kernel timing.  With profiling enabled the next links_simulate records HIP
- * events around each of its passes on the call's stream; links_last_timings
- * synchronises with the last recorded event and writes the elapsed milliseconds
- * of up to n passes, in this order: set-up count (validation, solve-order length,
- * bucket offsets), set-up fill (solve order and records at the sorted position),
- * FP32 pass, FP64 pass (hand-over list, or every candidate in FP64 precision),
- * compaction and path selection, path pass.  A pass
- * that did not run reports 0.  Returns the number of values written. */
+/* Kernel timing.  With profiling enabled every links_simulate records HIP
+ * events around each of its passes on the call's stream, into the next of 64
+ * event sets held by the context (a call with a low-fidelity screen records two
+ * sets, the screen's first).  Recording never synchronises the host, so a caller
+ * can time a run of calls and read them afterwards.  links_profile clears the
+ * sets.  links_last_timings synchronises with the last completed call's final
+ * event and writes the elapsed milliseconds of up to n passes, in this order:
+ * set-up count (validation, solve-order length, bucket offsets), set-up fill
+ * (solve order and records at the sorted position), FP32 pass, FP64 pass
+ * (hand-over list, or every candidate in FP64 precision), compaction and path
+ * selection, path pass.  links_mean_timings writes the mean of each pass over
+ * the last `calls` completed profiled calls (1 <= calls <= the number held,
+ * at most 64).  A pass that did not run counts as 0.  Both return the number of
+ * values written, or LINKS_ERR_ARG when no (or too few) profiled calls are held. */
 #define LINKS_TIMING_PASSES 6
 int links_profile(links_ctx* ctx, int enable);
 int links_last_timings(links_ctx* ctx, float* ms, int n);
+int links_mean_timings(links_ctx* ctx, int calls, float* ms, int n);
 
 #ifdef __cplusplus
 }

@@ -55,6 +55,12 @@ struct Buf {
 
 }  // namespace
 
+constexpr int kTimingRing = 64;
+struct TimingSet {
+  hipEvent_t ev[LINKS_TIMING_PASSES + 1] = {};
+  bool used[LINKS_TIMING_PASSES] = {};
+};
+
 struct links_ctx {
   int device = 0;
   int num_cu = 0;
@@ -81,11 +87,15 @@ struct links_ctx {
   std::map<std::string, int> occ_cache;
   // last call's statistics
   int last_grid32 = 0, last_grid64 = 0;
-  // profiling: events around the passes of the last links_simulate
+  // profiling: events around the passes of the last kTimingRing profiled
+  // links_simulate calls, one set per call, so that a caller can time many calls
+  // and read them afterwards without synchronising in between
   bool profile = false;
-  hipEvent_t ev[LINKS_TIMING_PASSES + 1] = {};
-  bool ev_used[LINKS_TIMING_PASSES] = {};
-  bool ev_ready = false;
+  TimingSet ev_ring[kTimingRing];
+  int ev_cur = 0;      // set the current profiled call records into
+  int ev_last = 0;     // set of the last completed profiled call
+  int ev_count = 0;    // completed profiled calls held, at most kTimingRing
+  bool ev_open = false;
   // graph capture: passes are enqueued without profiling events, and workspace
   // held by live graphs is never reallocated
   bool capturing = false;
@@ -181,9 +191,25 @@ int crank_table(links_ctx* ctx, int T, hipStream_t st, float2** cs32, double2** 
 
 // records the boundary event before pass i (i == LINKS_TIMING_PASSES: after the last)
 int mark(links_ctx* ctx, int i, hipStream_t st) {
-  if (!ctx->profile || ctx->capturing) return LINKS_OK;
-  if (!ctx->ev[i]) HIP_CHECK(hipEventCreate(&ctx->ev[i]));
-  HIP_CHECK(hipEventRecord(ctx->ev[i], st));
+  if (!ctx->ev_open) return LINKS_OK;
+  TimingSet& s = ctx->ev_ring[ctx->ev_cur];
+  if (!s.ev[i]) HIP_CHECK(hipEventCreate(&s.ev[i]));
+  HIP_CHECK(hipEventRecord(s.ev[i], st));
+  return LINKS_OK;
+}
+
+void mark_used(links_ctx* ctx, int i) {
+  if (ctx->ev_open) ctx->ev_ring[ctx->ev_cur].used[i] = true;
+}
+
+// elapsed milliseconds of each pass of one recorded set
+int read_set(links_ctx* ctx, const TimingSet& s, float* ms, int k) {
+  HIP_CHECK(hipEventSynchronize(s.ev[LINKS_TIMING_PASSES]));
+  for (int i = 0; i < k; i++) {
+    ms[i] = 0.f;
+    if (s.used[i]) HIP_CHECK(hipEventElapsedTime(&ms[i], s.ev[i], s.ev[i + 1]));
+  }
+  (void)ctx;
   return LINKS_OK;
 }
 
@@ -229,8 +255,9 @@ int links_create(int device, links_ctx** out) {
 void links_destroy(links_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
-  for (auto& e : ctx->ev)
-    if (e) (void)hipEventDestroy(e);
+  for (auto& set : ctx->ev_ring)
+    for (auto& e : set.ev)
+      if (e) (void)hipEventDestroy(e);
   for (auto& kv : ctx->bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
   if (ctx->hkeys) (void)hipHostFree(ctx->hkeys);
@@ -532,17 +559,22 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   pa.block_hist = block_hist;
   pa.block_off = block_off;
   pa.perm = perm;
-  for (int i = 0; i < LINKS_TIMING_PASSES; i++) ctx->ev_used[i] = false;
-  ctx->ev_ready = false;
+  // a profiled call takes the next event set of the ring
+  ctx->ev_open = ctx->profile && !ctx->capturing;
+  if (ctx->ev_open) {
+    ctx->ev_cur = ctx->ev_count == 0 ? 0 : (ctx->ev_last + 1) % kTimingRing;
+    if (ctx->ev_count == kTimingRing) ctx->ev_count--;  // the oldest set is re-recorded
+    for (int i = 0; i < LINKS_TIMING_PASSES; i++) ctx->ev_ring[ctx->ev_cur].used[i] = false;
+  }
   // set-up: validation and solve-order length, bucket offsets, then the records
   // written at each candidate's sorted position (largest solve order first)
   if ((rc = mark(ctx, 0, st))) return rc;
   HIP_CHECK(launch_prep_count(pa, st));
   HIP_CHECK(launch_prep_offsets(pa, st));
-  ctx->ev_used[0] = true;
+  mark_used(ctx, 0);
   if ((rc = mark(ctx, 1, st))) return rc;
   HIP_CHECK(launch_prep_fill(pa, st));
-  ctx->ev_used[1] = true;
+  mark_used(ctx, 1);
   if ((rc = mark(ctx, 2, st))) return rc;
 
   SimArgs sa;
@@ -611,7 +643,7 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
     c64.grid = grid_for(ctx, "sim64", sim64_blocks_per_cu(J, kFromPerm, true, c64.waves, lds64));
     if ((rc = mark(ctx, 3, st))) return rc;
     HIP_CHECK(run64(sa64, kFromPerm, true, c64, ctx->par64 == 2));
-    ctx->ev_used[3] = true;
+    mark_used(ctx, 3);
     ctx->last_grid32 = 0;
   } else {
     LaunchCfg c32;
@@ -626,7 +658,7 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
       c32.grid = grid_for(ctx, "sim32", sim32_blocks_per_cu(J, mode, T, c32.waves, lds32));
       HIP_CHECK(launch_sim32(sa, mode, c32, st));
     }
-    ctx->ev_used[2] = true;
+    mark_used(ctx, 2);
     c64.grid = grid_for(ctx, "sim64", sim64_blocks_per_cu(J, kFromEsc, ctx->exact_handover, c64.waves, lds64));
     if ((rc = mark(ctx, 3, st))) return rc;
     SimArgs h1 = sa64;
@@ -650,7 +682,7 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
       h2.deesc = 0;
       HIP_CHECK(launch_sim64(h2, kFromEsc, ctx->exact_handover, c64, st));
     }
-    ctx->ev_used[3] = true;
+    mark_used(ctx, 3);
     ctx->last_grid32 = c32.grid;
   }
   ctx->last_grid64 = c64.grid;
@@ -660,20 +692,24 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
     HIP_CHECK(launch_compact(B, out->status, scratch, out->path_index, out->cap, out->n_written, path_row, st));
     if (out->cap > 0)
       HIP_CHECK(launch_select_paths(B, perm, out->status, path_row, 0, scratch, path_list, counters, st));
-    ctx->ev_used[4] = true;
+    mark_used(ctx, 4);
   } else if (opts->write == LINKS_WRITE_ALL) {
     HIP_CHECK(launch_select_paths(B, perm, out->status, path_row, 1, scratch, path_list, counters, st));
-    ctx->ev_used[4] = true;
+    mark_used(ctx, 4);
   }
   // ---- path pass: the output joint of every selected candidate, step by step,
   // written straight into its output row
   if ((rc = mark(ctx, 5, st))) return rc;
   if (opts->write != LINKS_WRITE_NONE && !(opts->write == LINKS_WRITE_VALID && out->cap == 0)) {
     HIP_CHECK(run64(sa64, kFromPath, fp64, c64, ctx->par64 == 2));
-    ctx->ev_used[5] = true;
+    mark_used(ctx, 5);
   }
   if ((rc = mark(ctx, 6, st))) return rc;
-  ctx->ev_ready = ctx->profile && !ctx->capturing;
+  if (ctx->ev_open) {
+    ctx->ev_last = ctx->ev_cur;
+    ctx->ev_count++;
+  }
+  ctx->ev_open = false;
   return LINKS_OK;
 }
 
@@ -685,6 +721,7 @@ int links_simulate(links_ctx* ctx, const links_batch* batch, const links_sim_opt
                    void* stream) {
   return simulate_impl(ctx, batch, opts, out, stream, kRun);
 }
+
 
 int links_generate_dyads(links_ctx* ctx, uint64_t seed, int64_t first, int32_t B, int32_t J, int32_t n_lo,
                          int32_t n_hi, int32_t paper_mode, uint8_t* n, uint32_t* adj, uint32_t* fixed,
@@ -816,21 +853,36 @@ void links_graph_destroy(links_graph* graph) {
 int links_profile(links_ctx* ctx, int enable) {
   if (!ctx) return fail(LINKS_ERR_ARG, "ctx is NULL");
   ctx->profile = enable != 0;
-  ctx->ev_ready = false;
+  ctx->ev_count = 0;
+  ctx->ev_cur = ctx->ev_last = 0;
+  ctx->ev_open = false;
   return LINKS_OK;
 }
 
 int links_last_timings(links_ctx* ctx, float* ms, int n) {
   if (!ctx || (!ms && n > 0)) return fail(LINKS_ERR_ARG, "NULL argument");
-  if (!ctx->ev_ready) return fail(LINKS_ERR_ARG, "no profiled links_simulate call");
+  if (ctx->ev_count == 0) return fail(LINKS_ERR_ARG, "no profiled links_simulate call");
   int rc = set_device(ctx);
   if (rc) return rc;
-  HIP_CHECK(hipEventSynchronize(ctx->ev[LINKS_TIMING_PASSES]));
-  int k = n < LINKS_TIMING_PASSES ? n : LINKS_TIMING_PASSES;
-  for (int i = 0; i < k; i++) {
-    ms[i] = 0.f;
-    if (ctx->ev_used[i]) HIP_CHECK(hipEventElapsedTime(&ms[i], ctx->ev[i], ctx->ev[i + 1]));
+  const int k = n < LINKS_TIMING_PASSES ? (n > 0 ? n : 0) : LINKS_TIMING_PASSES;
+  if ((rc = read_set(ctx, ctx->ev_ring[ctx->ev_last], ms, k))) return rc;
+  return k;
+}
+
+int links_mean_timings(links_ctx* ctx, int calls, float* ms, int n) {
+  if (!ctx || (!ms && n > 0)) return fail(LINKS_ERR_ARG, "NULL argument");
+  if (calls < 1 || calls > ctx->ev_count)
+    return fail(LINKS_ERR_ARG, "calls = %d outside [1, %d profiled calls held]", calls, ctx->ev_count);
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  const int k = n < LINKS_TIMING_PASSES ? (n > 0 ? n : 0) : LINKS_TIMING_PASSES;
+  float sum[LINKS_TIMING_PASSES] = {}, one[LINKS_TIMING_PASSES];
+  for (int c = 0; c < calls; c++) {
+    const int slot = ((ctx->ev_last - c) % kTimingRing + kTimingRing) % kTimingRing;
+    if ((rc = read_set(ctx, ctx->ev_ring[slot], one, k))) return rc;
+    for (int i = 0; i < k; i++) sum[i] += one[i];
   }
+  for (int i = 0; i < k; i++) ms[i] = sum[i] / (float)calls;
   return k;
 }
 

@@ -52,6 +52,7 @@ class SimOut(ctypes.Structure):
 EXPORTS = ["links_create", "links_destroy", "links_last_error", "links_version", "links_solve_order",
            "links_sim_opts_default", "links_simulate", "links_normalize_paths", "links_set_tuning",
            "links_get_tuning", "links_set_option", "links_normalize_paths_n", "links_profile", "links_last_timings",
+           "links_mean_timings",
            "links_graph_create", "links_graph_launch", "links_graph_destroy", "links_get_option",
            "links_generate_dyads", "links_curate"]
 TIMING_PASSES = ["prep_count", "prep_fill", "fp32_pass", "fp64_pass", "compaction", "path_pass"]
@@ -102,6 +103,8 @@ def load() -> ctypes.CDLL:
     L.links_profile.restype = ctypes.c_int
     L.links_last_timings.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
     L.links_last_timings.restype = ctypes.c_int
+    L.links_mean_timings.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
+    L.links_mean_timings.restype = ctypes.c_int
     L.links_generate_dyads.argtypes = [P, ctypes.c_uint64, ctypes.c_int64, i32, i32, i32, i32, i32, P, P, P, P, P, P]
     L.links_generate_dyads.restype = ctypes.c_int
     L.links_curate.argtypes = [P, ctypes.POINTER(Batch), P, P, i32, i32, P, i32, ctypes.c_double, P, P, P, P]
@@ -228,6 +231,15 @@ class Context:
         k = load().links_last_timings(self._h, buf, n)
         if k < 0:
             _check(k, "links_last_timings")
+        return {name: float(buf[i]) for i, name in enumerate(TIMING_PASSES[:k])}
+
+    def mean_timings(self, calls: int) -> dict:
+        """Mean milliseconds of each pass over the last `calls` profiled simulate calls."""
+        n = len(TIMING_PASSES)
+        buf = (ctypes.c_float * n)()
+        k = load().links_mean_timings(self._h, calls, buf, n)
+        if k < 0:
+            _check(k, "links_mean_timings")
         return {name: float(buf[i]) for i, name in enumerate(TIMING_PASSES[:k])}
 
     # ------------------------------------------------------------------ solve order

@@ -37,3 +37,10 @@ def test_traffic_summary_parses():
     v = b.traffic_from_profile()
     # None only when the FP32 pass sources changed since the counters were taken
     assert v is None or 1e8 < v < 1e10
+
+
+def test_method_flop_counts():
+    """The roofline counts the method's own work: 30 FLOP per placement and 8 per
+    crank rotation, whatever the precision and its bookkeeping."""
+    b = _bench()
+    assert b.FLOP_DYAD == 30 and b.FLOP_TIP == 8

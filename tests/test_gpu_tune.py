@@ -38,3 +38,29 @@ def test_autotune_applies_and_caches(tmp_path):
     r2 = tune.autotune(ctx2, db, space=space, path=path)
     assert r2["cached"] and r2["config"] == r["config"]
     assert all(ctx2.get_option(k) == v for k, v in r["config"].items())
+
+
+def test_pass_timings_ring():
+    """Profiled calls record their pass timings without a host synchronisation;
+    the ring returns the last call's timings and means over up to 64 calls."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2208_14567_amd import links as L
+    print("[timings] dyad_6_20 20000", flush=True)
+    ctx = L.Context(0)
+    db = L.to_device(gen.workload("dyad_6_20", 20000, seed=9))
+    ctx.simulate(db)
+    ctx.profile(True)
+    with pytest.raises(L.LinksError):
+        ctx.mean_timings(1)                     # nothing recorded since profiling was enabled
+    for _ in range(70):                         # wraps the 64-set ring
+        ctx.simulate(db)
+    torch.cuda.synchronize()
+    last = ctx.last_timings()
+    assert ctx.mean_timings(1) == last
+    mean = ctx.mean_timings(64)
+    assert set(mean) == set(L.TIMING_PASSES)
+    assert mean["fp32_pass"] > 0 and mean["path_pass"] == 0 and mean["prep_fill"] > 0
+    with pytest.raises(L.LinksError):
+        ctx.mean_timings(65)
+    ctx.profile(False)
