@@ -390,7 +390,9 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
         } else {
           ++t;
         }
-      } else if (SRC == kFromPath && DMAX > 5) {
+      } else if (SRC == kFromPath && EXACT && DMAX > 11) {
+        // (the correctly rounded sequence above 13 joints needs every register for
+        // its arithmetic: a store per step)
         double2 po = P[out_slot * bd + tid];
         if (fail != 0) po = make_double2(__builtin_nan(""), __builtin_nan(""));
         const int t_stop = fail != 0 ? t_end : t + 1;
@@ -404,9 +406,10 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
         }
         if (fail != 0 || ++t >= t_end) done = true;
       } else if (SRC == kFromPath) {
-        // small mechanisms (few FLOP per path byte): the row is written 64 bytes at
-        // a time, the last K steps' positions staged in registers (K = 8 for f32
-        // paths, 4 for f64) and stored together
+        // the row is written 64 bytes at a time: the last K steps' positions staged
+        // in registers (K = 8 for f32 paths, 4 for f64) and stored together as four
+        // 16-byte pieces, so each lane's row reaches memory in whole 64-byte
+        // segments rather than one 8-byte store per step
         const int K = A.path_f64 ? 4 : 8;
         const int k = t & (K - 1);
         const int t_first = t - k;

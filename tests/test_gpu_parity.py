@@ -343,6 +343,36 @@ def test_small_mechanism_path_rows(ctx, L, T):
     assert np.isnan(ref["path"]).any() or T < 8
 
 
+@pytest.mark.parametrize("T", [7, 13, 200, 201])
+def test_path_rows_every_joint_count(ctx, L, T):
+    """Path rows of mechanisms of every size class (written in staged groups of
+    steps, or a store per step): FP64 rows equal the oracle's bit for bit in f64
+    and f32; with FP32 decisions the path pass's rows are within 1e-5 scale of the
+    oracle's and its f32 rows are its f64 rows rounded."""
+    _say(f"[rows, all sizes] T={T}")
+    b = gen.Batch.concat([gen.dyad_batch(1500, 90 + T, gen.n_uniform(4, 20), J=20),
+                          gen.dyad_batch(500, 91 + T, gen.n_uniform(20, 32), J=32)])
+    db = L.to_device(b)
+    ref = oracle.simulate(b, T=T, path=True, nthreads=NTH)
+    for precision in (L.FP64, L.FP32_RECHECK):
+        r64 = _np(ctx.simulate(db, T=T, precision=precision, write=L.WRITE_ALL, path_dtype=L.F64))
+        r32 = _np(ctx.simulate(db, T=T, precision=precision, write=L.WRITE_ALL, path_dtype=L.F32))
+        for k in ("status", "fail_step", "esc_step"):
+            assert np.array_equal(r64[k], r32[k]), (precision, k)
+        assert np.array_equal(r32["path"], r64["path"].astype(np.float32), equal_nan=True), precision
+        if precision == L.FP64:
+            assert np.array_equal(r64["status"], ref["status"])
+            assert np.array_equal(r64["path"], ref["path"], equal_nan=True)
+        else:
+            ok = (r64["status"] == ref["status"]) & (r64["fail_step"] == ref["fail_step"])
+            assert ok.mean() > 0.97
+            sc = _scale(b)[ok]
+            err = np.where(np.isnan(ref["path"][ok]), 0.0, np.abs(r64["path"][ok] - ref["path"][ok]))
+            assert np.array_equal(np.isnan(r64["path"][ok]), np.isnan(ref["path"][ok]))
+            assert np.all(err.max(axis=(1, 2)) <= 1e-5 * sc)
+    assert (ref["status"] == 0).sum() > 50
+
+
 def test_ragged_and_wide_strides(ctx, L):
     _say("[strides]")
     for J, lo, hi in ((7, 4, 7), (13, 6, 13), (32, 20, 32)):
