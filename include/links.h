@@ -188,6 +188,26 @@ typedef struct {
 int links_simulate(links_ctx* ctx, const links_batch* batch, const links_sim_opts* opts,
                    links_sim_out* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): links_simulate with the
+ * same arguments, kernels and results, whose workspace (records, work lists,
+ * hand-over queues, crank tables) lives in one fixed device array of
+ * LINKS_NOALLOC_SCRATCH_BYTES per GPU instead of memory the context allocates.
+ * The call allocates nothing, on the device or the host, and records no timing
+ * events.  The array is held by each GPU the library runs on until the process
+ * ends; links_create looks up its address on the context's device.  A call
+ * needs about (185 + 81 J) bytes per candidate (plus 16 J with x0_f32 input, and
+ * 4 ceil(T / 32) in FP64 precision with paths) after 96 KiB of crank tables: at
+ * J = 20 and T = 200 about 37,000 candidates fit.  Errors:
+ * those of links_simulate; LINKS_ERR_ARG, before any device work, when the call
+ * needs more than the array holds or T > 4096.  Every call on a GPU shares that
+ * GPU's array and leaves its contents behind (what must start at zero is cleared
+ * by each call): calls that overlap in time on one GPU race, so issue them on one
+ * stream or synchronise them. */
+#define LINKS_NOALLOC_SCRATCH_BYTES (64u << 20)
+int links_simulate_noalloc(links_ctx* ctx, const links_batch* batch, const links_sim_opts* opts,
+                           links_sim_out* out, void* stream);
+
 /* Launch parameters of the simulation passes (chosen by the autotuner in the
  * Python layer, or set by hand): waves32 / waves64 = wavefronts per workgroup of
  * the FP32 / FP64 pass (1..4); refill_min = idle lanes a wave waits for before it

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -100,6 +101,9 @@ struct links_ctx {
   // held by live graphs is never reallocated
   bool capturing = false;
   int graphs = 0;
+  // workspace carved from caller-provided device memory instead of allocated
+  // (the allocation-free entry point); null: ordinary allocations
+  links::Arena* arena = nullptr;
   // pinned host copy of the running retrieval result (FIRST scans)
   uint64_t* hkeys = nullptr;
   size_t hkeys_bytes = 0;
@@ -114,6 +118,20 @@ struct links_graph {
 namespace {
 
 int ensure(links_ctx* ctx, const char* name, size_t bytes, void** out) {
+  if (links::Arena* ar = ctx->arena) {
+    // the next 256-byte aligned piece of the arena; a dry pass only measures
+    const size_t off = (ar->used + 255) & ~(size_t)255;
+    ar->used = off + bytes;
+    if (ar->used > ar->peak) ar->peak = ar->used;
+    if (ar->dry) {
+      *out = nullptr;
+      return LINKS_OK;
+    }
+    if (ar->used > ar->cap)
+      return fail(LINKS_ERR_ARG, "workspace %s does not fit the %zu-byte scratch area", name, ar->cap);
+    *out = ar->base + off;
+    return LINKS_OK;
+  }
   Buf& b = ctx->bufs[name];
   if (b.bytes < bytes) {
     if (ctx->graphs > 0)
@@ -161,9 +179,48 @@ int check_batch(const links_batch* b) {
   return LINKS_OK;
 }
 
+// The crank table of the allocation-free path: at the start of the arena, room
+// for kArenaTableMax steps; uploaded through a fixed host staging buffer in
+// pieces (no allocation on either side), and kept while T stays the same.
+constexpr int kStage = 512;
+std::mutex g_stage_mu;
+double2 g_stage64[kStage];
+float2 g_stage32[kStage];
+
+int arena_crank_table(links_ctx* ctx, links::Arena* ar, int T, hipStream_t st, float2** cs32, double2** cs64) {
+  (void)ctx;
+  if (T > links::kArenaTableMax)
+    return fail(LINKS_ERR_ARG, "T = %d above %d, the most the allocation-free path holds", T, links::kArenaTableMax);
+  if (ar->dry) {
+    *cs64 = nullptr;
+    *cs32 = nullptr;
+    return LINKS_OK;
+  }
+  *cs64 = reinterpret_cast<double2*>(ar->base);
+  *cs32 = reinterpret_cast<float2*>(ar->base + (size_t)links::kArenaTableMax * sizeof(double2));
+  if (*ar->table_T == T) return LINKS_OK;
+  std::lock_guard<std::mutex> lock(g_stage_mu);
+  for (int t0 = 0; t0 < T; t0 += kStage) {
+    const int m = T - t0 < kStage ? T - t0 : kStage;
+    for (int i = 0; i < m; i++) {
+      const int t = t0 + i;
+      double theta = 2.0 * M_PI * (double)t / (double)T;
+      double c = cos(theta), s = sin(theta);
+      g_stage64[i] = make_double2(c, s);
+      g_stage32[i] = make_float2((float)c, (float)s);
+    }
+    HIP_CHECK(hipMemcpyAsync(*cs64 + t0, g_stage64, sizeof(double2) * m, hipMemcpyHostToDevice, st));
+    HIP_CHECK(hipMemcpyAsync(*cs32 + t0, g_stage32, sizeof(float2) * m, hipMemcpyHostToDevice, st));
+    HIP_CHECK(hipStreamSynchronize(st));  // the staging buffer is reused
+  }
+  *ar->table_T = T;
+  return LINKS_OK;
+}
+
 // theta_t = 2 pi t / T, counter-clockwise, evaluated in double on the host; one
 // table per T, so that a recorded graph keeps its own table
 int crank_table(links_ctx* ctx, int T, hipStream_t st, float2** cs32, double2** cs64) {
+  if (links::Arena* ar = ctx->arena) return arena_crank_table(ctx, ar, T, st, cs32, cs64);
   const std::string k64 = "cs64:" + std::to_string(T), k32 = "cs32:" + std::to_string(T);
   int rc = ensure_t(ctx, k64.c_str(), (size_t)T, cs64);
   if (rc) return rc;
@@ -248,6 +305,11 @@ int links_create(int device, links_ctx** out) {
     return fail(LINKS_ERR_DEVICE, "hipGetDeviceProperties: %s", hipGetErrorString(e));
   }
   ctx->num_cu = prop.multiProcessorCount;
+  // the device address of this device's allocation-free scratch area, once per device
+  if ((rc = links::noalloc_setup(device))) {
+    delete ctx;
+    return rc;
+  }
   *out = ctx;
   return LINKS_OK;
 }
@@ -453,6 +515,9 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   }
 
   using namespace links;
+  // each pass of a call (a low-fidelity screen runs two) carves the arena anew
+  // after the crank tables
+  if (ctx->arena) ctx->arena->used = kArenaTableBytes;
   // single-precision positions: widened to double once (exactly), then the same path
   links_batch wide;
   if (!batch->x0) {
@@ -722,6 +787,43 @@ int links_simulate(links_ctx* ctx, const links_batch* batch, const links_sim_opt
   return simulate_impl(ctx, batch, opts, out, stream, kRun);
 }
 
+}  // extern "C"
+
+namespace links {
+
+int ctx_device(const links_ctx* ctx) { return ctx->device; }
+
+int report_error(int code, const char* msg) { return fail(code, "%s", msg); }
+
+// links_simulate with every workspace buffer carved from [base, base + cap): a dry
+// pass measures the call's needs (no device work), then the call runs with
+// profiling events off (creating them would allocate)
+int simulate_in_arena(links_ctx* ctx, const links_batch* batch, const links_sim_opts* opts, links_sim_out* out,
+                      void* stream, unsigned char* base, size_t cap, int* table_T) {
+  if (!ctx) return fail(LINKS_ERR_ARG, "ctx is NULL");
+  if (ctx->capturing) return fail(LINKS_ERR_ARG, "the context is capturing a graph");
+  Arena dry{nullptr, cap, kArenaTableBytes, kArenaTableBytes, true, table_T};
+  ctx->arena = &dry;
+  int rc = simulate_impl(ctx, batch, opts, out, stream, kPrepare);
+  ctx->arena = nullptr;
+  if (rc) return rc;
+  if (dry.peak > cap)
+    return fail(LINKS_ERR_ARG,
+                "B = %d, J = %d needs %zu bytes of workspace, above the %zu-byte allocation-free scratch area",
+                batch->B, batch->J, dry.peak, cap);
+  Arena run{base, cap, kArenaTableBytes, kArenaTableBytes, false, table_T};
+  const bool prof = ctx->profile;
+  ctx->profile = false;
+  ctx->arena = &run;
+  rc = simulate_impl(ctx, batch, opts, out, stream, kRun);
+  ctx->arena = nullptr;
+  ctx->profile = prof;
+  return rc;
+}
+
+}  // namespace links
+
+extern "C" {
 
 int links_generate_dyads(links_ctx* ctx, uint64_t seed, int64_t first, int32_t B, int32_t J, int32_t n_lo,
                          int32_t n_hi, int32_t paper_mode, uint8_t* n, uint32_t* adj, uint32_t* fixed,

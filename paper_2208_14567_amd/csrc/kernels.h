@@ -1,6 +1,7 @@
 // kernels.h -- launchers of the device kernels (internal to liblinks.so).
 #pragma once
 #include "common.h"
+#include "links.h"
 
 namespace links {
 
@@ -17,6 +18,21 @@ constexpr int kCntOff = 40;     // [32] bucket offsets
 constexpr int kCntCur = 72;     // [32] next item of each bucket (FP32 pass)
 constexpr int kCntRes = 104;    // candidates returned from the FP64 hand-over to FP32
 constexpr int kCntSize = 112;
+
+// Workspace carved from a fixed device area instead of allocated (the
+// allocation-free entry point).  The area starts with the crank tables of up to
+// kArenaTableMax steps (FP64 then FP32); the call's buffers follow, each at a
+// 256-byte boundary.  A dry pass only measures what a call needs.
+constexpr int kArenaTableMax = 4096;
+constexpr size_t kArenaTableBytes = (size_t)kArenaTableMax * (sizeof(double2) + sizeof(float2));
+struct Arena {
+  unsigned char* base;  // device address of the area (null on a dry pass)
+  size_t cap;           // its size in bytes
+  size_t used;          // end of the last piece carved
+  size_t peak;          // largest end over the passes of one call
+  bool dry;
+  int* table_T;         // steps of the crank table the area holds now (-1: none)
+};
 
 struct PrepArgs {
   int32_t B, J;
@@ -167,5 +183,13 @@ hipError_t launch_chamfer(const ChamferArgs& a, hipStream_t st);
 hipError_t launch_chamfer_merge(const ChamferArgs& a, uint64_t* running, int64_t* idx, float* dist,
                                 hipStream_t st);
 hipError_t launch_chamfer_clear(uint64_t* running, int64_t n, hipStream_t st);
+
+// set-up and entry of the allocation-free variant of links_simulate
+// (noalloc.hip, api.cpp)
+int noalloc_setup(int device);
+int simulate_in_arena(links_ctx* ctx, const links_batch* batch, const links_sim_opts* opts, links_sim_out* out,
+                      void* stream, unsigned char* base, size_t cap, int* table_T);
+int ctx_device(const links_ctx* ctx);
+int report_error(int code, const char* msg);
 
 }  // namespace links

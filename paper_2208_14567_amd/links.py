@@ -52,7 +52,7 @@ class SimOut(ctypes.Structure):
 EXPORTS = ["links_create", "links_destroy", "links_last_error", "links_version", "links_solve_order",
            "links_sim_opts_default", "links_simulate", "links_normalize_paths", "links_set_tuning",
            "links_get_tuning", "links_set_option", "links_normalize_paths_n", "links_profile", "links_last_timings",
-           "links_mean_timings",
+           "links_mean_timings", "links_simulate_noalloc",
            "links_graph_create", "links_graph_launch", "links_graph_destroy", "links_get_option",
            "links_generate_dyads", "links_curate"]
 TIMING_PASSES = ["prep_count", "prep_fill", "fp32_pass", "fp64_pass", "compaction", "path_pass"]
@@ -103,6 +103,8 @@ def load() -> ctypes.CDLL:
     L.links_profile.restype = ctypes.c_int
     L.links_last_timings.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
     L.links_last_timings.restype = ctypes.c_int
+    L.links_simulate_noalloc.argtypes = L.links_simulate.argtypes
+    L.links_simulate_noalloc.restype = ctypes.c_int
     L.links_mean_timings.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
     L.links_mean_timings.restype = ctypes.c_int
     L.links_generate_dyads.argtypes = [P, ctypes.c_uint64, ctypes.c_int64, i32, i32, i32, i32, i32, P, P, P, P, P, P]
@@ -296,6 +298,20 @@ class Context:
                                            tau_drift, out, T_prefilter, branch)
         _check(load().links_simulate(self._h, ctypes.byref(cb), ctypes.byref(opts), ctypes.byref(so), _stream(stream)),
                "links_simulate")
+        return res
+
+    def simulate_noalloc(self, b: DeviceBatch, T: int = 200, precision: int = FP32_RECHECK, write: int = WRITE_NONE,
+                         out_joint: int = -1, path_dtype: int = F32, cap: Optional[int] = None,
+                         eps_disc: float = 1e-6, eps_branch: float = 1e-5, tau_drift: float = 1e-4,
+                         out: Optional[dict] = None, stream=None, T_prefilter: int = 0,
+                         branch: int = BRANCH_CONTINUITY):
+        """``simulate`` through links_simulate_noalloc: the library's workspace is the
+        device's fixed scratch array (the output tensors are still the caller's;
+        pass ``out`` to allocate nothing here either)."""
+        cb, opts, so, res = self._sim_args(b, T, precision, write, out_joint, path_dtype, cap, eps_disc, eps_branch,
+                                           tau_drift, out, T_prefilter, branch)
+        _check(load().links_simulate_noalloc(self._h, ctypes.byref(cb), ctypes.byref(opts), ctypes.byref(so),
+                                             _stream(stream)), "links_simulate_noalloc")
         return res
 
     def generate_dyads(self, B: int, seed: int, first: int = 0, J: int = 20, n_lo: int = 6, n_hi: int = 20,
