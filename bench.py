@@ -306,10 +306,10 @@ def next_config(args, L, gen):
     ctx = L.Context(0)
     per_n = 2_000_000
     table = {}
-    for paper in (False, True):
+    for paper, rules in ((False, False), (True, False), (False, True), (True, True)):
         rows = []
-        for n in range(4, 21):
-            db = ctx.generate_dyads(per_n, seed=900 + n, J=20, n_lo=n, n_hi=n, paper_mode=paper)
+        for n in range(5 if rules else 4, 21):
+            db = ctx.generate_dyads(per_n, seed=900 + n, J=20, n_lo=n, n_hi=n, paper_mode=paper, rules=rules)
             r = ctx.simulate(db, T=T)
             st = r["status"].cpu().numpy()
             valid = int((st == 0).sum())
@@ -319,7 +319,8 @@ def next_config(args, L, gen):
             if n in (6, 12, 20):
                 # the first 20,000 against the oracle, decisions outside the bands
                 k = 20_000
-                sub = gen.dyad_batch(k, 900 + n, gen.n_uniform(n, n), J=20, paper_mode=paper)  # the same draws
+                sub = gen.dyad_batch(k, 900 + n, gen.n_uniform(n, n), J=20, paper_mode=paper,
+                                     rules=rules)  # the same draws
                 if paper:
                     sub = gen.standardize_paper(sub)  # as the device generator places pivot and tip
                 ref = oracle.simulate(sub, T=T, margins=True, nthreads=threads)
@@ -327,8 +328,9 @@ def next_config(args, L, gen):
                 row["oracle_sample"] = {"candidates": k, "out_of_band": int(clear.sum()),
                                         "status_equal": float((st[:k][clear] == ref["status"][clear]).mean())}
             rows.append(row)
-            log(f"{'paper' if paper else 'dyad'} n={n}: {valid} valid of {per_n}")
-        table["paper_mode" if paper else "dyad"] = rows
+            name = ("paper_mode" if paper else "dyad") + ("_rules" if rules else "")
+            log(f"{name} n={n}: {valid} valid of {per_n}")
+        table[name] = rows
     # low-fidelity screen (50 positions, then 200 for the survivors) on the headline workload
     host = gen.workload("dyad_6_20", args.B, seed=2)
     db = L.to_device(host, dev)

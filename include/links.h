@@ -270,15 +270,22 @@ int links_normalize_paths_n(links_ctx* ctx, const float* paths, const int32_t* c
  * Positions"): joint 0 fixed pivot, joint 1 actuated tip (link 0-1), joint 2
  * fixed, and each joint k = 3..n-1 linked to two earlier joints that are not both
  * fixed (21 draws of a pair, then the arm 0-1 as a fallback); n ~ U{n_lo..n_hi};
- * every coordinate uniform in [0,1) with 24 random bits.  paper_mode = 1 adds, with
- * probability 1/4, a linkless fixed joint in place of a linked one and sets the
- * arm to pivot (0.5, 0.5), tip (0.55, 0.5).  Candidate i of the call is candidate
+ * every coordinate uniform in [0,1) with 24 random bits.  paper_mode is a bit
+ * set: bit 0 adds, with probability 1/4, a fixed joint in place of a linked one
+ * and sets the arm to pivot (0.5, 0.5), tip (0.55, 0.5); bit 1 applies the
+ * paper's topology rules (the last joint depends on every other joint, so the
+ * mechanism is not reducible, and is linked to no fixed joint): a draw is kept
+ * only if the rules can still be met by the joints left to add, else the
+ * deterministic choice that uses up the most joints not yet used by any later
+ * joint is taken, and the last joint takes those left (needs n_lo >= 5).
+ * Candidate i of the call is candidate
  * first + i of the seed's sequence (SplitMix64 streams, Steele, Lea and Flood
  * 2014), identical to the host generator of the Python package for the same
  * seed, so a long stream can be generated in independent chunks.
  * Outputs are device arrays in the links_batch layout (x0 as double), written
  * asynchronously on `stream`.  Errors: LINKS_ERR_ARG for B < 0, first < 0,
- * J outside [3, 32], joint counts outside [3, J], or a NULL array. */
+ * J outside [3, 32], joint counts outside [3, J], paper_mode outside 0..3, the
+ * rules with n_lo < 5, or a NULL array. */
 int links_generate_dyads(links_ctx* ctx, uint64_t seed, int64_t first, int32_t B, int32_t J, int32_t n_lo,
                          int32_t n_hi, int32_t paper_mode, uint8_t* n, uint32_t* adj, uint32_t* fixed,
                          uint8_t* motor, double* x0, void* stream);

@@ -833,7 +833,8 @@ int links_generate_dyads(links_ctx* ctx, uint64_t seed, int64_t first, int32_t B
   if (J < 3 || J > links::kMaxJ) return fail(LINKS_ERR_ARG, "J = %d outside [3, 32]", J);
   if (n_lo < 3 || n_lo > n_hi || n_hi > J)
     return fail(LINKS_ERR_ARG, "joint counts [%d, %d] not within [3, J = %d]", n_lo, n_hi, J);
-  if (paper_mode != 0 && paper_mode != 1) return fail(LINKS_ERR_ARG, "paper_mode must be 0 or 1");
+  if (paper_mode < 0 || paper_mode > 3) return fail(LINKS_ERR_ARG, "paper_mode must be in 0..3");
+  if ((paper_mode & 2) && n_lo < 5) return fail(LINKS_ERR_ARG, "the topology rules need at least 5 joints");
   if (B > 0 && (!n || !adj || !fixed || !motor || !x0)) return fail(LINKS_ERR_ARG, "NULL output array");
   int rc = set_device(ctx);
   if (rc) return rc;
@@ -844,7 +845,8 @@ int links_generate_dyads(links_ctx* ctx, uint64_t seed, int64_t first, int32_t B
   g.J = J;
   g.n_lo = n_lo;
   g.n_hi = n_hi;
-  g.paper_mode = paper_mode;
+  g.paper_mode = paper_mode & 1;
+  g.rules = (paper_mode >> 1) & 1;
   g.n = n;
   g.adj = adj;
   g.fixed = fixed;

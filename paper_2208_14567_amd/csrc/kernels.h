@@ -88,6 +88,7 @@ struct GenArgs {
   int64_t first;   // index of the first candidate in the seed's sequence
   int64_t B;
   int32_t J, n_lo, n_hi, paper_mode;
+  int32_t rules;   // the paper's topology rules (irreducible, last joint not on a fixed joint)
   uint8_t* n;
   uint32_t* adj;
   uint32_t* fixed;

@@ -154,42 +154,88 @@ def n_mixture(bands: Sequence[tuple], weights: Sequence[float]) -> Callable[[np.
 # --------------------------------------------------------------------------- dyad-built topologies
 
 def dyad_batch(B: int, seed: int, n_dist: Callable[[np.ndarray], np.ndarray], J: int = 20,
-               paper_mode: bool = False, first: int = 0, chunk: int = 1 << 20) -> Batch:
+               paper_mode: bool = False, first: int = 0, chunk: int = 1 << 20, rules: bool = False) -> Batch:
     """Random 1-DOF candidates built by repeated dyad addition (J operator).
 
     Joint 0 is the fixed pivot, joint 1 the actuated tip (link 0-1), joint 2 a fixed
     joint; joints 3..n-1 are each linked to two existing joints that are not both
     fixed.  All positions are uniform in [0,1)^2.  ``first`` offsets the candidate
     index so a large batch can be produced in independent chunks.
+
+    ``rules`` applies the paper's two topology rules ("Generating Valid
+    Topologies"): the last joint depends on every other joint (the mechanism is
+    not reducible), and it is linked to no fixed joint.  Each operator draw is
+    kept only if the rules can still be met by the joints left to add (see
+    ``_rules_feasible``); after the attempt budget a deterministic choice that
+    uses up the most pending joints is taken.  Needs n >= 5.
     """
     out = empty_batch(B, J)
     for lo in range(0, B, chunk):
         hi = min(B, lo + chunk)
-        _dyad_chunk(out, lo, hi, seed, n_dist, J, paper_mode, first)
+        _dyad_chunk(out, lo, hi, seed, n_dist, J, paper_mode, first, rules)
     return out
 
 
-def _dyad_chunk(out: Batch, lo: int, hi: int, seed: int, n_dist, J: int, paper_mode: bool, first: int):
+def _popcount(x: np.ndarray) -> np.ndarray:
+    x = x.astype(np.uint64)
+    c = np.zeros(x.shape, np.int64)
+    for b in range(32):
+        c += ((x >> np.uint64(b)) & np.uint64(1)).astype(np.int64)
+    return c
+
+
+def _lowest(mask: np.ndarray) -> np.ndarray:
+    """Index of the lowest set bit of each mask (32 where none)."""
+    m = mask.astype(np.uint64)
+    out = np.full(m.shape, 32, np.int64)
+    for b in range(31, -1, -1):
+        out = np.where(((m >> np.uint64(b)) & np.uint64(1)) == 1, b, out)
+    return out
+
+
+def _rules_feasible(U: np.ndarray, fixed: np.ndarray, r: np.ndarray) -> np.ndarray:
+    """Whether the topology rules can still be met with r joints left to add after
+    the current one.  U holds the pending joints: placed or fixed joints that no
+    later joint uses yet (each must still lead to the last joint).  Every further
+    joint except the last can use up at most two pending joints, at most one of
+    them fixed (two fixed parents are not allowed), and adds itself; the last one
+    must use up all that remain, at most two, none fixed.  So: |U| <= r + 1 and
+    at most r - 1 pending fixed joints."""
+    return (_popcount(U) <= r + 1) & (_popcount(U & fixed) <= r - 1)
+
+
+def _dyad_chunk(out: Batch, lo: int, hi: int, seed: int, n_dist, J: int, paper_mode: bool, first: int,
+                rules: bool = False):
     m = hi - lo
     cand = np.arange(first + lo, first + hi, dtype=np.uint64)
     st = stream_state(seed, cand)
     n = n_dist(draw_u24(st, DRAW_N)).astype(np.int64)
     if n.min() < 3 or n.max() > J:
         raise ValueError("joint count distribution outside [3, J]")
+    if rules and n.min() < 5:
+        raise ValueError("the topology rules need at least 5 joints")
     adj = np.zeros((m, J), np.uint32)
     fixed = np.full(m, 0b101, np.uint32)
     one = np.uint32(1)
     adj[:, 0] |= one << np.uint32(1)
     adj[:, 1] |= one << np.uint32(0)
     rows = np.arange(m)
+    U = np.full(m, 0b110, np.uint32)     # pending joints (rules): the tip and fixed joint 2
     for k in range(3, J):
         act = n > k
         if not act.any():
             break
         base = DRAW_TOPO + 64 * (k - 3)
+        bit = one << np.uint32(k)
+        r = n - 1 - k                     # joints still to add after this one
+        last = act & (r == 0)
         if paper_mode:
             is_g = act & (draw_u24(st, base) < 0.25)
-            fixed = np.where(is_g, fixed | (one << np.uint32(k)), fixed)
+            if rules:
+                is_g &= ~last & _rules_feasible(U | bit, fixed | bit, r)
+            fixed = np.where(is_g, fixed | bit, fixed)
+            if rules:
+                U = np.where(is_g, U | bit, U)
         else:
             is_g = np.zeros(m, bool)
         need = act & ~is_g
@@ -204,15 +250,51 @@ def _dyad_chunk(out: Batch, lo: int, hi: int, seed: int, n_dist, J: int, paper_m
             i = np.floor(ui * k).astype(np.int64).clip(0, k - 1)
             j = np.floor(uj * (k - 1)).astype(np.int64).clip(0, k - 2)
             j = np.where(j >= i, j + 1, j)
-            both_fixed = (((fixed >> i.astype(np.uint32)) & one) == one) & \
-                         (((fixed >> j.astype(np.uint32)) & one) == one)
+            fi = ((fixed >> i.astype(np.uint32)) & one) == one
+            fj = ((fixed >> j.astype(np.uint32)) & one) == one
+            both_fixed = fi & fj
             take = ~done & ~both_fixed
+            if rules:
+                # the last joint's parents are fixed by the rules (below); any other
+                # draw is kept if the rules can still be met afterwards
+                pair = (one << i.astype(np.uint32)) | (one << j.astype(np.uint32))
+                take &= ~last & _rules_feasible((U & ~pair) | bit, fixed, r)
             pi = np.where(take, i, pi)
             pj = np.where(take, j, pj)
             done |= take
-        # deterministic fallback after the attempt budget: the actuator arm (0, 1)
-        pi = np.where(done, pi, 0)
-        pj = np.where(done, pj, 1)
+        if rules:
+            nonfixed = ((one << np.uint32(k)) - one) & ~fixed
+            uf, un = U & fixed, U & ~fixed
+            # no draw kept: the choice that uses up the most pending joints, a
+            # pending fixed one first, then pending non-fixed ones, then the lowest
+            # non-fixed joint
+            g1 = np.where(uf != 0, _lowest(uf), np.where(un != 0, _lowest(un), _lowest(nonfixed)))
+            m1 = one << np.minimum(g1, 31).astype(np.uint32)
+            g2 = np.where((un & ~m1) != 0, _lowest(un & ~m1), _lowest(nonfixed & ~m1))
+            # the last joint: the one or two pending joints (never fixed by then);
+            # with one, a partner among the other non-fixed joints, the q-th in
+            # index order with q from the draw of the first attempt's first partner
+            l1 = _lowest(un)
+            ml = one << np.minimum(l1, 31).astype(np.uint32)
+            others = nonfixed & ~ml
+            q = np.floor(draw_u24(st, base + 1) * np.maximum(_popcount(others), 1)).astype(np.int64)
+            partner = np.full(m, 32, np.int64)
+            seen = np.zeros(m, np.int64)
+            for bb in range(32):
+                has = ((others >> np.uint32(bb)) & one) == one
+                partner = np.where(has & (seen == q), bb, partner)
+                seen += has
+            l2 = np.where((un & ~ml) != 0, _lowest(un & ~ml), partner)
+            pi = np.where(done, pi, np.where(last, l1, g1))
+            pj = np.where(done, pj, np.where(last, l2, g2))
+            if np.any(need & ((pi > 31) | (pj > 31))):
+                raise RuntimeError("topology rules: no parents left (generator bug)")
+            pair = (one << pi.astype(np.uint32)) | (one << pj.astype(np.uint32))
+            U = np.where(need, (U & ~pair) | bit, U)
+        else:
+            # deterministic fallback after the attempt budget: the actuator arm (0, 1)
+            pi = np.where(done, pi, 0)
+            pj = np.where(done, pj, 1)
         kk = np.uint32(k)
         sel = rows[need]
         adj[sel, k] |= (one << pi[need].astype(np.uint32)) | (one << pj[need].astype(np.uint32))
@@ -324,6 +406,9 @@ def workload(name: str, B: Optional[int] = None, seed: Optional[int] = None, fir
     dyad_skewed    n: 60% U{6..8}, 30% U{9..14}, 10% U{15..20}
     dyad_4_20      n ~ U{4..20} (serving requests)
     paper_8_20     paper-mode generation (N_g with p=1/4, standardised actuator), n ~ U{8..20}
+    paper_rules_8_20  the same with the paper's topology rules (not reducible, last
+                   joint linked to no fixed joint)
+    dyad_rules_6_20   dyad_6_20 with the topology rules
     """
     if name == "fourbar":
         return fourbar_batch(B or 10_000, 1 if seed is None else seed, True, first=first)
@@ -339,6 +424,12 @@ def workload(name: str, B: Optional[int] = None, seed: Optional[int] = None, fir
     if name == "paper_8_20":
         return standardize_paper(dyad_batch(B or 100_000, 6 if seed is None else seed, n_uniform(8, 20),
                                             20, paper_mode=True, first=first))
+    if name == "paper_rules_8_20":
+        return standardize_paper(dyad_batch(B or 100_000, 10 if seed is None else seed, n_uniform(8, 20),
+                                            20, paper_mode=True, first=first, rules=True))
+    if name == "dyad_rules_6_20":
+        return dyad_batch(B or 1_000_000, 11 if seed is None else seed, n_uniform(6, 20), 20, first=first,
+                          rules=True)
     raise KeyError(name)
 
 

@@ -316,9 +316,10 @@ class Context:
 
     def generate_dyads(self, B: int, seed: int, first: int = 0, J: int = 20, n_lo: int = 6, n_hi: int = 20,
                        paper_mode: bool = False, device=None, out: Optional[DeviceBatch] = None,
-                       stream=None) -> DeviceBatch:
+                       stream=None, rules: bool = False) -> DeviceBatch:
         """Generates candidates first .. first+B-1 of the seed's sequence on the
-        device (the same candidates as gen.dyad_batch with n ~ U{n_lo..n_hi})."""
+        device (the same candidates as gen.dyad_batch with n ~ U{n_lo..n_hi}, the
+        same paper_mode and rules)."""
         dev = torch.device("cuda", self.device) if device is None else device
         if out is None:
             out = DeviceBatch(torch.empty(B, dtype=torch.uint8, device=dev),
@@ -327,7 +328,7 @@ class Context:
                               torch.empty((B, 2), dtype=torch.uint8, device=dev),
                               torch.empty((B, J, 2), dtype=torch.float64, device=dev))
         _check(load().links_generate_dyads(self._h, seed & 0xFFFFFFFFFFFFFFFF, first, B, J, n_lo, n_hi,
-                                           1 if paper_mode else 0, _ptr(out.n), _ptr(out.adj), _ptr(out.fixed),
+                                           (1 if paper_mode else 0) | (2 if rules else 0), _ptr(out.n), _ptr(out.adj), _ptr(out.fixed),
                                            _ptr(out.motor), _ptr(out.x0), _stream(stream)), "links_generate_dyads")
         return out
 

@@ -37,7 +37,8 @@ def _mobility(b):
     return m
 
 
-@pytest.mark.parametrize("name", ["dyad_6_20", "dyad_skewed", "dyad_4_20", "paper_8_20"])
+@pytest.mark.parametrize("name", ["dyad_6_20", "dyad_skewed", "dyad_4_20", "paper_8_20", "paper_rules_8_20",
+                                  "dyad_rules_6_20"])
 def test_dyad_topologies_have_mobility_one(name):
     b = gen.workload(name, 400, seed=9)
     assert np.all(_mobility(b) == 1)
@@ -91,3 +92,45 @@ def test_near_copies_shift_the_start_and_add_noise():
         assert any(np.array_equal(near[i], np.roll(src, -k, axis=0)) for k in range(40))
     noisy = gen.near_copies(base, 2, 0.01, seed=9)
     assert not np.array_equal(noisy, gen.near_copies(base, 2, 0.0, seed=9))
+
+
+def _rule_violations(b):
+    """Per candidate: (not every joint lies in the dependency closure of the last
+    joint of the graphical solver's order, the last joint is linked to a fixed
+    joint).  The closure follows each placed joint to its two solve-order parents
+    and the tip to the pivot."""
+    import oracle
+    order, nd, _, st = oracle.solve_order(b)
+    assert np.all(st == 0)
+    red, fix = np.zeros(b.B, bool), np.zeros(b.B, bool)
+    for c in range(b.B):
+        n, D, fx = int(b.n[c]), int(nd[c]), int(b.fixed[c])
+        par = {int(e[0]): (int(e[1]), int(e[2])) for e in order[c, :D]}
+        par[1] = (0,)
+        last = int(order[c, D - 1, 0])
+        seen, todo = set(), [last]
+        while todo:
+            j = todo.pop()
+            if j not in seen:
+                seen.add(j)
+                todo.extend(par.get(j, ()))
+        red[c] = len(seen) != n
+        fix[c] = any((int(b.adj[c, last]) >> f) & 1 and (fx >> f) & 1 for f in range(n))
+    return red, fix
+
+
+@pytest.mark.parametrize("paper", [False, True])
+def test_topology_rules(paper):
+    """The paper's topology rules ("Generating Valid Topologies"): with them every
+    candidate's last solved joint depends on all other joints and touches no fixed
+    joint; without them many candidates break both rules."""
+    lo = 8 if paper else 5
+    b = gen.dyad_batch(3000, 31, gen.n_uniform(lo, 20), J=20, paper_mode=paper, rules=True)
+    red, fix = _rule_violations(b)
+    assert not red.any() and not fix.any()
+    b0 = gen.dyad_batch(3000, 31, gen.n_uniform(lo, 20), J=20, paper_mode=paper, rules=False)
+    red0, fix0 = _rule_violations(b0)
+    assert red0.mean() > 0.5 and fix0.mean() > 0.05
+    # the rules cannot be met below five joints
+    with pytest.raises(ValueError):
+        gen.dyad_batch(10, 1, gen.n_uniform(4, 6), rules=True)
