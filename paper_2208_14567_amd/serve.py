@@ -103,6 +103,9 @@ class Request:
     # per tick share: (first request-local index of the share, valid indices, device paths [k, T, 2]);
     # ticks on different streams can finish out of order
     pieces: List[Tuple[int, np.ndarray, object]] = field(default_factory=list)
+    # events after the copies of each of its shares (a request can span ticks on
+    # both lanes); it is retired only once every one of them has completed
+    copy_events: List[object] = field(default_factory=list)
     source: object = None             # DeviceBatch until admitted
 
     @property
@@ -270,6 +273,7 @@ class Server:
         reqs = [(r.rid, r.start, r.size) for r in self.active]
         by_id = {r.rid: r for r in self.active}
         finished = []
+        touched = []
         a0 = lo % self.capacity
         with torch.cuda.stream(lane.stream):
             for rid, first, last in overlaps(lo, hi, reqs):
@@ -284,15 +288,24 @@ class Server:
                 if p1 > p0:
                     r.pieces.append((first, idx[p0:p1] - r.start, lane.path[p0:p1].clone()))
                 r.done += last - first
+                touched.append(r)
                 if r.done == r.size:
                     finished.append(r)
             ev = torch.cuda.Event()
             ev.record(lane.stream)
+        for r in touched:
+            r.copy_events.append(ev)
         lane.copies = (ev, finished)
 
     def _retire(self, lane: _Lane):
         ev, finished = lane.copies
         lane.copies = None
+        for r in finished:
+            # its shares copied on the other lane may still be in flight: its ring
+            # slots are freed, and its latency stamped, once all of them are done
+            for e in r.copy_events:
+                e.synchronize()
+            r.copy_events.clear()
         now = time.perf_counter()
         for r in finished:
             r.finished_at = now
