@@ -225,7 +225,8 @@ def stream_config(args, L, gen, oracle, tune, dev, threads):
     # tune once on a generated chunk, then use the setting on both lanes
     first = lanes[0]
     first["ctx"].generate_dyads(CH, seed, first=0, out=first["batch"])
-    tuned = tune.autotune(first["ctx"], first["batch"], T=T, precision=L.FP32_RECHECK, use_cache=False)
+    tuned = tune.autotune(first["ctx"], first["batch"], T=T, precision=L.FP32_RECHECK, use_cache=False,
+                          write=L.WRITE_VALID, cap=cap)
     tune.apply(lanes[1]["ctx"], tuned["config"])
     sample_chunks = {0, nch // 2, nch - 1}
     sample = {}
@@ -619,7 +620,7 @@ def main():
     tuned = None
     if not args.no_tune:
         t0 = time.time()
-        tuned = tune.autotune(ctx, db, T=T, precision=L.FP32_RECHECK, use_cache=False)
+        tuned = tune.autotune(ctx, db, T=T, precision=L.FP32_RECHECK, use_cache=False, write=L.WRITE_VALID, cap=B)
         log(f"autotune: {tuned['config']} ({tuned['ms']:.3f} ms, {tuned['measurements']} runs, {time.time() - t0:.1f}s)")
     out = {"status": torch.empty(B, dtype=torch.uint8, device=dev),
            "fail_step": torch.empty(B, dtype=torch.int16, device=dev),
@@ -684,7 +685,7 @@ def main():
         ctx64 = L.Context(0)
         tuned64 = None
         if not args.no_tune:
-            tuned64 = tune.autotune(ctx64, db, T=T, precision=L.FP64, use_cache=False,
+            tuned64 = tune.autotune(ctx64, db, T=T, precision=L.FP64, use_cache=False, write=L.WRITE_VALID, cap=B,
                                     space={"chunk": tune.SPACE["chunk"], "refill64": [1, 8, 32]})
             log(f"autotune fp64: {tuned64['config']} ({tuned64['ms']:.3f} ms)")
         sec64, pass64 = run(ctx64, L.FP64, "fp64 plain")

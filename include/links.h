@@ -197,7 +197,7 @@ int links_simulate(links_ctx* ctx, const links_batch* batch, const links_sim_opt
  * events.  The array is held by each GPU the library runs on until the process
  * ends; links_create looks up its address on the context's device.  A call
  * needs about (185 + 81 J) bytes per candidate (plus 16 J with x0_f32 input, and
- * 4 ceil(T / 32) in FP64 precision with paths) after 96 KiB of crank tables: at
+ * 4 ceil(T / 32) when path rows are written) after 96 KiB of crank tables: at
  * J = 20 and T = 200 about 37,000 candidates fit.  Errors:
  * those of links_simulate; LINKS_ERR_ARG, before any device work, when the call
  * needs more than the array holds or T > 4096.  Every call on a GPU shares that
@@ -240,7 +240,20 @@ int links_set_tuning(links_ctx* ctx, int waves32, int refill_min, int waves64);
  *                     (default) or 16 (the other parallel passes use 16);
  *   "par32"           1: the FP32 pass runs parallel in time the same way (same
  *                     decisions and hand-over steps as the step-by-step pass);
- *                     0 (default).  Ignored when "deesc" > 0. */
+ *                     0 (default).  Ignored when "deesc" > 0;
+ *   "drain32"         once the FP32 pass's work list is exhausted, its waves with
+ *                     fewer active lanes than this hand their candidates (column,
+ *                     error bounds, next step) to the parallel-in-time FP32 pass,
+ *                     which carries them on with the same decisions (0..65; 0,
+ *                     the default: never; 65: every wave at once);
+ *   "sort_esc"        1: the FP64 hand-over pass takes its queue ordered by
+ *                     hand-over step, earliest first; 0 (default): as handed over;
+ *   "path_chunks"     1 (default): path rows are computed in chunks of 32 steps,
+ *                     each on a lane of its own, from the sides of every placed
+ *                     joint that the decision passes record at the chunk ends
+ *                     (FP64 and FP32_RECHECK precision; not with "par32",
+ *                     "drain32", "deesc" > 0 or "par64" = 2); 0: whole rows.  Rows
+ *                     are the same either way. */
 int links_set_option(links_ctx* ctx, const char* name, int value);
 /* Current value of a named option in *value (LINKS_ERR_ARG for an unknown name). */
 int links_get_option(links_ctx* ctx, const char* name, int* value);

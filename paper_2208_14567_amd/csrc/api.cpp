@@ -85,6 +85,17 @@ struct links_ctx {
   // off by default: its larger LDS footprint per wave costs more than the idle
   // lanes it saves on the measured workloads
   bool par32 = false;
+  // drain hand-off of the FP32 pass: once the work list is exhausted, waves of the
+  // step-by-step pass with fewer than drain32 active lanes hand their candidates
+  // to the parallel-in-time pass (0: never; 65: every wave at once)
+  int drain32 = 0;
+  // the FP64 hand-over pass takes the queue ordered by hand-over step, earliest
+  // first (the candidates with the most FP64 steps ahead start first); off by
+  // default: on the measured workloads the queue as handed over is faster
+  bool sort_esc = false;
+  // path rows computed in chunks of kPathChunk steps from the sides the decision
+  // passes record (else whole, step by step)
+  bool path_chunks = true;
   std::map<std::string, int> occ_cache;
   // last call's statistics
   int last_grid32 = 0, last_grid64 = 0;
@@ -386,6 +397,21 @@ int links_set_option(links_ctx* ctx, const char* name, int value) {
     ctx->par32 = value != 0;
     return LINKS_OK;
   }
+  if (k == "path_chunks") {
+    if (value != 0 && value != 1) return fail(LINKS_ERR_ARG, "path_chunks must be 0 or 1");
+    ctx->path_chunks = value != 0;
+    return LINKS_OK;
+  }
+  if (k == "sort_esc") {
+    if (value != 0 && value != 1) return fail(LINKS_ERR_ARG, "sort_esc must be 0 or 1");
+    ctx->sort_esc = value != 0;
+    return LINKS_OK;
+  }
+  if (k == "drain32") {
+    if (value < 0 || value > 65) return fail(LINKS_ERR_ARG, "drain32 must be in 0..65");
+    ctx->drain32 = value;
+    return LINKS_OK;
+  }
   if (k == "seg64") {
     if (value != 4 && value != 8 && value != 16) return fail(LINKS_ERR_ARG, "seg64 must be 4, 8 or 16");
     ctx->seg64 = value;
@@ -413,6 +439,9 @@ int links_get_option(links_ctx* ctx, const char* name, int* value) {
   else if (k == "par64") *value = ctx->par64;
   else if (k == "seg64") *value = ctx->seg64;
   else if (k == "par32") *value = ctx->par32 ? 1 : 0;
+  else if (k == "drain32") *value = ctx->drain32;
+  else if (k == "sort_esc") *value = ctx->sort_esc ? 1 : 0;
+  else if (k == "path_chunks") *value = ctx->path_chunks ? 1 : 0;
   else return fail(LINKS_ERR_ARG, "unknown option '%s'", name);
   return LINKS_OK;
 }
@@ -555,14 +584,35 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   int32_t* scratch;
   uint32_t* side_ck = nullptr;
   const size_t nblocks = (size_t)prep_blocks(B);
-  // FP64 precision: path rows in chunks of kPathChunk steps, each on a lane of
-  // its own, starting from the sides the step-by-step FP64 pass records at the
-  // chunk boundaries.  (With FP32 decisions recording the sides costs the FP32
-  // pass about what the path pass gains, so those rows are computed whole.)
+  // Path rows in chunks of kPathChunk steps, each on a lane of its own, starting
+  // from the sides the decision passes record at the chunk boundaries (the FP32
+  // pass for the steps it decides, the FP64 passes for theirs).  Rows are
+  // computed whole with the parallel-in-time FP32 pass, its drain hand-off, the
+  // return to FP32 after a hand-over, or par64 = 2; and without escalation
+  // (FP32_ONLY), whose FP32 sides near a tie need not be those the FP64 path
+  // pass takes.
   const int ck_n = (T + kPathChunk - 1) / kPathChunk;
-  const bool chunks = opts->precision == LINKS_FP64 && opts->write != LINKS_WRITE_NONE &&
-                      !(opts->write == LINKS_WRITE_VALID && out->cap == 0) && ck_n > 1 && ctx->par64 != 2;
+  const bool chunks = ctx->path_chunks && opts->write != LINKS_WRITE_NONE &&
+                      !(opts->write == LINKS_WRITE_VALID && out->cap == 0) && ck_n > 1 && ctx->par64 != 2 &&
+                      (opts->precision == LINKS_FP64 ||
+                       (opts->precision == LINKS_FP32_RECHECK && !ctx->par32 && ctx->deesc == 0 && ctx->drain32 == 0));
   if (chunks && (rc = ensure_t(ctx, "side_ck", (size_t)B * ck_n, &side_ck))) return rc;
+  // drain hand-off: the parallel-in-time pass's counters, its work queue and the
+  // handed-on error bounds
+  const bool drain = opts->precision != LINKS_FP64 && ctx->drain32 > 0 && !ctx->par32 && ctx->deesc == 0;
+  int32_t* cnt_drain = nullptr;
+  EscEntry* drain_q = nullptr;
+  uint16_t* drain_err = nullptr;
+  const bool sort_esc = opts->precision != LINKS_FP64 && ctx->sort_esc && ctx->deesc == 0;
+  EscEntry* esc_sorted = nullptr;
+  int32_t* esc_work = nullptr;
+  if (sort_esc && ((rc = ensure_t(ctx, "esc_sorted", B, &esc_sorted)) ||
+                   (rc = ensure_t(ctx, "esc_work", 2 * kEscBins, &esc_work))))
+    return rc;
+  if (drain && ((rc = ensure_t(ctx, "cnt_drain", kCntSize, &cnt_drain)) ||
+                (rc = ensure_t(ctx, "drain_q", B, &drain_q)) ||
+                (rc = ensure_t(ctx, "drain_err", (size_t)B * J, &drain_err))))
+    return rc;
   if ((rc = ensure_t(ctx, "meta", B, &meta)) || (rc = ensure_t(ctx, "cf", B, &cf)) ||
       (rc = ensure_t(ctx, "cd", B, &cd)) || (rc = ensure_t(ctx, "df", (size_t)B * J, &df)) ||
       (rc = ensure_t(ctx, "dd", (size_t)B * J, &dd)) || (rc = ensure_t(ctx, "x0s", (size_t)B * J, &x0s)) ||
@@ -588,6 +638,7 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   if (opts->write == LINKS_WRITE_ALL)
     HIP_CHECK(launch_fill_u32(out->path, (size_t)B * T * elt / 4, 0xFFFFFFFFu, st));  // NaN rows
   HIP_CHECK(launch_fill_u32(counters, kCntSize, 0u, st));
+  if (drain) HIP_CHECK(launch_fill_u32(cnt_drain, kCntSize, 0u, st));
   int16_t* fail_step = out->fail_step ? out->fail_step : fail_ws;
 
   PrepArgs pa;
@@ -681,6 +732,8 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   sa.res_pos = res_pos;
   sa.deesc = 0;
   sa.resume = 0;
+  sa.esc_cnt = counters + kCntEsc;
+  sa.mig_min = 0;
   sa.chunk = ctx->chunk;
   sa.branch = opts->branch;
   sa.side_ck = side_ck;
@@ -714,20 +767,43 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
     LaunchCfg c32;
     c32.waves = ctx->waves32;
     c32.refill_min = ctx->refill_min;
-    const int mode = opts->precision == LINKS_FP32_ONLY ? 1 : 0;
+    // mode bit 0: no escalation; bit 2: the pass records the sides at chunk ends
+    const int mode = (opts->precision == LINKS_FP32_ONLY ? 1 : 0) | (chunks ? 4 : 0);
     if (ctx->par32 && ctx->deesc == 0) {
       c32.grid = grid_for(ctx, "par32", sim32_par_blocks_per_cu(J, mode, T, c32.waves));
       HIP_CHECK(launch_sim32_par(sa, mode, c32, st));
     } else {
       const int lds32 = sim32_lds_bytes(J, c32.waves, T);
       c32.grid = grid_for(ctx, "sim32", sim32_blocks_per_cu(J, mode, T, c32.waves, lds32));
-      HIP_CHECK(launch_sim32(sa, mode, c32, st));
+      SimArgs s0 = sa;
+      if (drain) {
+        s0.mig_min = ctx->drain32;
+        s0.mig_out = drain_q;
+        s0.mig_cnt = cnt_drain + kCntItems;
+        s0.mig_err = drain_err;
+      }
+      HIP_CHECK(launch_sim32(s0, mode, c32, st));
+      if (drain) {
+        // the candidates the waves handed on, parallel in time from their step
+        SimArgs sp = sa;
+        sp.counters = cnt_drain;
+        sp.resume = 2;
+        sp.mig_in = drain_q;
+        sp.mig_err = drain_err;
+        LaunchCfg cp = c32;
+        cp.grid = grid_for(ctx, "par32", sim32_par_blocks_per_cu(J, mode, T, cp.waves));
+        HIP_CHECK(launch_sim32_par(sp, mode, cp, st));
+      }
     }
     mark_used(ctx, 2);
     c64.grid = grid_for(ctx, "sim64", sim64_blocks_per_cu(J, kFromEsc, ctx->exact_handover, c64.waves, lds64));
     if ((rc = mark(ctx, 3, st))) return rc;
     SimArgs h1 = sa64;
     h1.deesc = ctx->deesc;
+    if (sort_esc) {
+      HIP_CHECK(launch_sort_esc(B, counters, esc, esc_work, esc_sorted, st));
+      h1.esc = esc_sorted;
+    }
     const bool par_h = ctx->par64 >= 1 && ctx->deesc == 0;
     HIP_CHECK(run64(h1, kFromEsc, ctx->exact_handover, c64, par_h));
     if (ctx->deesc > 0) {
@@ -736,6 +812,7 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
       HIP_CHECK(launch_resume_setup(counters, counters2, st));
       SimArgs r32 = sa;
       r32.counters = counters2;
+      r32.esc_cnt = counters2 + kCntEsc;
       r32.resume = 1;
       r32.esc = esc2;
       r32.esc_pos = esc2_pos;

@@ -131,7 +131,20 @@ struct SimArgs {
   EscEntry* res;       // [B] (sorted position, next step)
   float2* res_pos;     // [B][J] slot positions at the end of the last FP64 step
   int32_t deesc;       // 0: the FP64 pass finishes every candidate it takes
-  int32_t resume;
+  int32_t resume;      // FP32 pass work items: 0 the sorted list, 1 the FP64 pass's returns (res),
+                       // 2 (parallel-in-time pass) the candidates the step-by-step pass handed on
+  // Drain hand-off of the FP32 pass.  Once the work list is exhausted, a wave of
+  // the step-by-step pass with fewer than mig_min active lanes stops: each active
+  // lane's column goes to esc_pos and its error bounds to mig_err (at the
+  // candidate's sorted position), and (sorted position, next step) to mig_out,
+  // counted in *mig_cnt.  The parallel-in-time pass (resume = 2) then carries
+  // them on bit for bit from mig_in, with full segments.  mig_min = 0: none.
+  int32_t mig_min;
+  EscEntry* mig_out;
+  int32_t* mig_cnt;
+  const EscEntry* mig_in;
+  uint16_t* mig_err;       // [B][J] error bounds (as the pass stores them) by sorted position
+  int32_t* esc_cnt;        // hand-over queue counter shared by the launches of the FP32 pass
 };
 
 }  // namespace links

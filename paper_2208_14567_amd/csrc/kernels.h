@@ -114,6 +114,11 @@ struct CurateArgs {
 };
 hipError_t launch_curate(const CurateArgs& a, hipStream_t st);
 size_t compact_scratch_ints(int32_t B);
+// the hand-over queue (counters[kCntEsc] entries of q) into out, ordered by
+// hand-over step in groups of 8 steps, earliest first; work: 2 kEscBins ints
+constexpr int kEscBins = 4096;
+hipError_t launch_sort_esc(int32_t B, const int32_t* counters, const EscEntry* q, int32_t* work, EscEntry* out,
+                           hipStream_t st);
 hipError_t launch_compact(int32_t B, const uint8_t* status, int32_t* scratch, int32_t* index, int32_t cap,
                           int32_t* total, int32_t* row_of, hipStream_t st);
 // path list over sorted positions: valid candidates with a row (all_simulated = 0)

@@ -802,7 +802,7 @@ hipError_t launch_prep_fill(const PrepArgs& a, hipStream_t st) {
 
 __global__ void resume_setup_kernel(const int32_t* counters, int32_t* counters2) {
   const int i = threadIdx.x;
-  if (i < kCntSize) counters2[i] = 0;
+  for (int k = i; k < kCntSize; k += blockDim.x) counters2[k] = 0;
   __syncthreads();
   if (i == 0) {
     const int r = counters[kCntRes];
@@ -838,6 +838,85 @@ hipError_t launch_fill_u32(void* p, size_t n_u32, uint32_t v, hipStream_t st) {
 }
 
 size_t compact_scratch_ints(int32_t B) { return (size_t)((B + kScanBlock - 1) / kScanBlock) + 1; }
+
+// ---- the hand-over queue ordered by hand-over step, earliest first: a candidate
+// handed over early may have the most FP64 steps ahead of it, so the FP64 pass
+// starts those first and its last waves are not left with long runs.  Key = the
+// step / 8 (at most kEscBins keys); entries with equal keys keep no particular
+// order (each is a candidate of its own).
+constexpr int kEscBlock = 1024;
+
+__global__ void __launch_bounds__(kEscBlock) esc_hist_kernel(const int32_t* counters, const EscEntry* q,
+                                                             int32_t* hist) {
+  __shared__ int32_t h[kEscBins];
+  for (int i = threadIdx.x; i < kEscBins; i += kEscBlock) h[i] = 0;
+  __syncthreads();
+  const int n = counters[kCntEsc];
+  const int i = blockIdx.x * kEscBlock + threadIdx.x;
+  if (i < n) atomicAdd(&h[min((int)q[i].t >> 3, kEscBins - 1)], 1);
+  __syncthreads();
+  for (int k = threadIdx.x; k < kEscBins; k += kEscBlock)
+    if (h[k]) atomicAdd(&hist[k], h[k]);
+}
+
+__global__ void __launch_bounds__(kEscBlock) esc_scan_kernel(int32_t* hist, int32_t* cursor) {
+  // exclusive prefix over kEscBins keys, one block
+  __shared__ int32_t part[kEscBlock];
+  constexpr int per = kEscBins / kEscBlock;
+  const int b = threadIdx.x * per;
+  int sum = 0;
+  for (int k = 0; k < per; ++k) sum += hist[b + k];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (int w = 1; w < kEscBlock; w <<= 1) {
+    const int add = threadIdx.x >= w ? part[threadIdx.x - w] : 0;
+    __syncthreads();
+    part[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int run = part[threadIdx.x] - sum;
+  for (int k = 0; k < per; ++k) {
+    const int c = hist[b + k];
+    cursor[b + k] = run;
+    run += c;
+  }
+}
+
+__global__ void __launch_bounds__(kEscBlock) esc_scatter_kernel(const int32_t* counters, const EscEntry* q,
+                                                                int32_t* cursor, EscEntry* out) {
+  __shared__ int32_t h[kEscBins];
+  for (int i = threadIdx.x; i < kEscBins; i += kEscBlock) h[i] = 0;
+  __syncthreads();
+  const int n = counters[kCntEsc];
+  const int i = blockIdx.x * kEscBlock + threadIdx.x;
+  int key = 0, rank = 0;
+  EscEntry e;
+  if (i < n) {
+    e = q[i];
+    key = min((int)e.t >> 3, kEscBins - 1);
+    rank = atomicAdd(&h[key], 1);
+  }
+  __syncthreads();
+  // one range per key of this block
+  for (int k = threadIdx.x; k < kEscBins; k += kEscBlock)
+    if (h[k]) h[k] = atomicAdd(&cursor[k], h[k]);
+  __syncthreads();
+  if (i < n) out[h[key] + rank] = e;
+}
+
+hipError_t launch_sort_esc(int32_t B, const int32_t* counters, const EscEntry* q, int32_t* work, EscEntry* out,
+                           hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  int32_t* hist = work;
+  int32_t* cursor = work + kEscBins;
+  hipError_t e = launch_fill_u32(hist, kEscBins, 0u, st);
+  if (e != hipSuccess) return e;
+  const int nb = (B + kEscBlock - 1) / kEscBlock;
+  hipLaunchKernelGGL(esc_hist_kernel, dim3(nb), dim3(kEscBlock), 0, st, counters, q, hist);
+  hipLaunchKernelGGL(esc_scan_kernel, dim3(1), dim3(kEscBlock), 0, st, hist, cursor);
+  hipLaunchKernelGGL(esc_scatter_kernel, dim3(nb), dim3(kEscBlock), 0, st, counters, q, cursor, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_compact(int32_t B, const uint8_t* status, int32_t* scratch, int32_t* index, int32_t cap,
                           int32_t* total, int32_t* row_of, hipStream_t st) {

@@ -65,8 +65,10 @@ sim32_kernel(SimArgs A) {
   // A finished candidate's results are written later, for all finished lanes of
   // the wave together (at the next refill or when the wave leaves): its lane is
   // idle meanwhile and keeps its slots in LDS for the hand-over dump.
-  int fin = 0;  // 0 nothing pending, 1 locked or degenerate, 2 handed over, 3 valid
-  int fcand = 0, fkind = 0, fstep = 0;
+  // 0 nothing pending, 1 locked, 2 handed over, 3 valid, 4 degenerate; the step of
+  // a failure or hand-over stays in t until the results are written
+  int fin = 0;
+  int fcand = 0;
   const bool orient = A.branch != 0;  // sides fixed at the start (else continuity)
   uint32_t obits = 0u;                // starting side of each placed joint
   int dmax_w = 0;  // largest solve order among the wave's lanes (uniform)
@@ -143,30 +145,64 @@ sim32_kernel(SimArgs A) {
   // positions of the handed-over candidates at their sorted-position rows
   auto flush = [&]() {
     if (__ballot(fin != 0) == 0ull) return;
-    if (fin == 1 || fin == 3) {
-      A.status[fcand] = (uint8_t)(fin == 3 ? 0 : fkind);
-      A.fail_step[fcand] = (int16_t)(fin == 3 ? -1 : fstep);
-      if (A.esc_step && !A.resume) A.esc_step[fcand] = -1;
+    if (fin == 1 || fin == 3 || fin == 4) {
+      A.status[fcand] = (uint8_t)(fin == 3 ? 0 : fin == 4 ? 2 : 1);
+      A.fail_step[fcand] = (int16_t)(fin == 3 ? -1 : t);
+      if (A.esc_step && A.resume != 1) A.esc_step[fcand] = -1;
     }
     const uint64_t em = __ballot(fin == 2);
     if (em != 0ull) {
       const int leader = __ffsll((unsigned long long)em) - 1;
       int base = 0;
-      if (lane_id() == leader) base = atomicAdd(&A.counters[kCntEsc], __popcll(em));
+      if (lane_id() == leader) base = atomicAdd(A.esc_cnt, __popcll(em));
       base = __shfl(base, leader);
       if (fin == 2) {
         EscEntry e;
         e.item = item;
-        e.t = (int16_t)fstep;
+        e.t = (int16_t)t;
         e.from_x0 = force64 ? 1 : 0;
         e.pad = 0;
         A.esc[base + mbcnt64(em)] = e;
         float2* dump = A.esc_pos + (size_t)item * J;  // the candidate's own row
         for (int sl = 0; sl < n; ++sl) dump[sl] = P[sl * bd + tid];
-        if (A.esc_step && !A.resume) A.esc_step[fcand] = (int16_t)fstep;  // the first hand-over
+        if (A.esc_step && A.resume != 1) A.esc_step[fcand] = (int16_t)t;  // the first hand-over
       }
     }
     fin = 0;
+  };
+
+  // Drain hand-off: once the work list is exhausted, a wave with fewer than
+  // mig_min active lanes stops, and each active lane leaves its column (positions
+  // into esc_pos, error bounds into mig_err, at its candidate's sorted position)
+  // and (sorted position, next step) in mig_out, counted in *mig_cnt, for the
+  // parallel-in-time pass to finish with full segments.
+  bool handing = false;  // wave-uniform
+  auto hand_off = [&]() {
+    const bool live = cand >= 0;
+    if (live) {
+      float2* dp = A.esc_pos + (size_t)item * J;
+      uint16_t* de = A.mig_err + (size_t)item * J;
+      for (int sl = 0; sl < n; ++sl) {
+        dp[sl] = P[sl * bd + tid];
+        de[sl] = E[sl * bd + tid];
+      }
+    }
+    const uint64_t m = __ballot(live);
+    if (m != 0ull) {
+      const int leader = __ffsll((unsigned long long)m) - 1;
+      int base = 0;
+      if (lane_id() == leader) base = atomicAdd(A.mig_cnt, __popcll(m));
+      base = __shfl(base, leader);
+      if (live) {
+        EscEntry e;
+        e.item = item;
+        e.t = (int16_t)t;
+        e.from_x0 = 0;
+        e.pad = 0;
+        A.mig_out[base + mbcnt64(m)] = e;
+      }
+    }
+    cand = -1;
   };
 
   for (;;) {
@@ -175,6 +211,11 @@ sim32_kernel(SimArgs A) {
     int nidle = __popcll(idle);
     if (nidle == kWave && exhausted) {
       flush();
+      break;
+    }
+    if (exhausted && kWave - nidle < A.mig_min) {
+      flush();
+      handing = true;
       break;
     }
     if (!exhausted && nidle > 0 && (nidle >= rm || nidle == kWave)) {
@@ -238,7 +279,7 @@ sim32_kernel(SimArgs A) {
           int t0 = 0;
           const float2* init = A.x0s + p;
           size_t init_stride = (size_t)Bs;
-          if (A.resume) {
+          if (A.resume == 1) {
             const EscEntry e = A.res[p];
             init = A.res_pos + (size_t)p * J;
             init_stride = 1;
@@ -297,6 +338,7 @@ sim32_kernel(SimArgs A) {
                 E[(g + k) * bd + tid] = bound_up(uu * (fabsf(xq[k].x) + fabsf(xq[k].y)));  // rounding of x0 to FP32
               }
           }
+
         }
       }
       // claim the next chunk ahead of time, after the record loads so that
@@ -334,6 +376,7 @@ sim32_kernel(SimArgs A) {
 
     bool ev = force64, lock_ev = false;
     int lock_kind = 1;
+    uint32_t sb = 0u;  // MODE & 4: the side taken by every placed joint at this step
     // branch-free placement loop: the trip count is the wave's largest solve order
     // (uniform); lanes past their own D or past an event keep their old values
 #pragma unroll
@@ -363,6 +406,7 @@ sim32_kernel(SimArgs A) {
       const float sg = fmaf(pr.x - bx, ox, (pr.y - by) * oy);
       // continuity: the side of the previous position; orientation: the starting side
       const bool left = orient ? ((obits >> s) & 1u) != 0u : sg >= 0.f;
+      if (MODE & 4) sb |= (left ? 1u : 0u) << s;
       const float sgn = left ? 1.f : -1.f;
       const float nx = fmaf(sgn, ox, bx), ny = fmaf(sgn, oy, by);
       bool write;
@@ -376,15 +420,19 @@ sim32_kernel(SimArgs A) {
         const float d = d2 * rd;
         const float h = 0.5f * sK * rd;
         const float sensK = 4.f * d * fabsf(fmaf(0.5f, S + Dm, -d2));
-        const float kthr = fmaf(sensK, Eab, KB);
-        const float mthr = fmaf(Eab, fmaf(TS, rd, 1.f), EB + Ep);
+        // K's own FP32 evaluation (S and Dm rounded from FP64, d^2, the two
+        // differences and the product) is within 9 units of (S + d^2)(d^2 + Dm)
+        const float kthr = fmaf(sensK, Eab, fmaf(2.5f * uu, (S + d2) * (d2 + Dm), KB));
+        // rounding of this placement (foot and normal), as a position error
+        const float R = fmaf(uu, fabsf(pa.x) + fabsf(pa.y), U2);
+        const float mthr = fmaf(Eab, fmaf(TS, rd, 1.f), EB + Ep + R);
         const bool band = (int)(fabsf(K) < kthr) | (int)(d2 < CD) | (int)(!orient && fabsf(sg) < mthr * h);
         const bool lock = K < 0.f;
         lock_ev = lock_ev | (act & !band & lock);
         ev = ev | (act & (band | lock));
         write = act & !band & !lock;
         const float A2 = 0.5f * (S - Dm) * rK;  // 2 ra rb / sqrt(K)
-        Ek = A2 * (Eab + fmaf(uu, fabsf(pa.x) + fabsf(pa.y), U2));
+        Ek = A2 * (Eab + R);
       } else {
         const bool deg = d2 <= DG;
         const bool lock = K < 0.f;
@@ -400,13 +448,15 @@ sim32_kernel(SimArgs A) {
 
     bool done = false;
     if (ev) {
-      fin = lock_ev ? 1 : 2;
-      fkind = lock_kind;
-      fstep = t;
+      fin = lock_ev ? (lock_kind == 2 ? 4 : 1) : 2;
       done = true;
     } else if (++t == T) {
       fin = 3;
       done = true;
+    } else if ((MODE & 4) && (t & (kPathChunk - 1)) == 0) {
+      // the sides of the step that ends a chunk of the path row (read by the
+      // chunked path pass)
+      A.side_ck[(size_t)cand * A.ck_n + t / kPathChunk] = sb;
     }
     if (done) {
       fcand = cand;
@@ -414,6 +464,7 @@ sim32_kernel(SimArgs A) {
     }
     }
   }
+  if (handing) hand_off();
 }
 
 template <int DMAX, int MODE>
@@ -466,11 +517,14 @@ enum : int { kE32None = 0, kE32Lock = 1, kE32Degenerate = 2, kE32Band = 3, kE32S
 
 // LDS: positions [nslot][bd] f32x2 and error bounds [nslot][bd] u16; per segment
 // two tables of DMAX entries (S, Dm, Kc, parent slots: the live candidate's and the
-// next one's), the next candidate's reference positions [32], CandF32 [16] and
-// meta, index and sorted position; the crank table when it fits.
+// next one's), the next candidate's reference positions [32], CandF32 [16],
+// meta, index, sorted position and first step, and the reference error bounds
+// [32] of a candidate handed on by the step-by-step pass; the crank table when it
+// fits.
 template <int DMAX>
 __host__ __device__ constexpr size_t par32_seg_bytes() {
-  return 2 * DMAX * sizeof(float4) + 32 * sizeof(float2) + 16 * sizeof(float) + 4 * sizeof(int);
+  return 2 * DMAX * sizeof(float4) + 32 * sizeof(float2) + 16 * sizeof(float) + 4 * sizeof(int) +
+         32 * sizeof(uint16_t);
 }
 
 template <int DMAX>
@@ -491,7 +545,8 @@ __global__ void __launch_bounds__(256) simpar32_kernel(SimArgs A) {
   float4* Ct = reinterpret_cast<float4*>(seg);                      // [2][DMAX]
   float2* PN = reinterpret_cast<float2*>(seg + 2 * DMAX * sizeof(float4));  // [32]
   float* CFN = reinterpret_cast<float*>(PN + 32);                   // [16]
-  int* MCN = reinterpret_cast<int*>(CFN + 16);                      // meta, index, sorted position
+  int* MCN = reinterpret_cast<int*>(CFN + 16);                      // meta, index, sorted position, step
+  uint16_t* EN = reinterpret_cast<uint16_t*>(MCN + 4);              // [32] bounds of a handed-on candidate
   constexpr bool tab_lds = (MODE & 2) == 0;
   float2* tab = reinterpret_cast<float2*>(segs + (size_t)(bd / kSeg32) * par32_seg_bytes<DMAX>());
   const int T = A.T;
@@ -523,6 +578,8 @@ __global__ void __launch_bounds__(256) simpar32_kernel(SimArgs A) {
   float pf_cf = 0.f;
   DyadF32 pf_q0, pf_q1;
   float2 pf_w0 = make_float2(0.f, 0.f), pf_w1 = make_float2(0.f, 0.f);
+  uint16_t pf_e0 = 0, pf_e1 = 0;
+  int pf_t0 = 0;
   pf_q0.S = pf_q0.Dm = pf_q0.Kc = 0.f;
   pf_q0.slots = 0u;
   pf_q1 = pf_q0;
@@ -561,7 +618,7 @@ __global__ void __launch_bounds__(256) simpar32_kernel(SimArgs A) {
         DG = CFN[11];
         obits = __float_as_uint(CFN[12]);  // CandF32::side
         cpar ^= 1;
-        t0 = 0;
+        t0 = MCN[3];  // 0, or the next step of a candidate handed on mid-rotation
         fresh = true;
         restarts = 0;
         has_staged = false;
@@ -571,7 +628,8 @@ __global__ void __launch_bounds__(256) simpar32_kernel(SimArgs A) {
           if (sl < n) {
             const float2 v = PN[sl];
             P[sl * bd + tid] = v;
-            E[sl * bd + tid] = bound_up(uu * (fabsf(v.x) + fabsf(v.y)));  // rounding of x0 to FP32
+            // rounding of x0 to FP32, or the bound a handed-on candidate carried
+            E[sl * bd + tid] = A.resume == 2 ? EN[sl] : bound_up(uu * (fabsf(v.x) + fabsf(v.y)));
           }
       }
       __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): LDS operations of a wave complete in order
@@ -644,6 +702,12 @@ __global__ void __launch_bounds__(256) simpar32_kernel(SimArgs A) {
           need_next = false;
           if (p >= 0) {
             in_flight = true;
+            pf_t0 = 0;
+            if (A.resume == 2) {  // a work item is a handed-on candidate
+              const EscEntry e = A.mig_in[p];
+              p = e.item;
+              pf_t0 = e.t;
+            }
             pf_p = p;
             pf_c = A.perm[p];
             pf_meta = reinterpret_cast<const uint32_t*>(A.meta)[p];
@@ -653,8 +717,16 @@ __global__ void __launch_bounds__(256) simpar32_kernel(SimArgs A) {
             const int s0 = min(r, J - 1), s1 = min(r + kSeg32, J - 1);
             pf_q0 = A.df[(size_t)s0 * Bs + p];
             pf_q1 = A.df[(size_t)s1 * Bs + p];
-            pf_w0 = A.x0s[(size_t)s0 * Bs + p];
-            pf_w1 = A.x0s[(size_t)s1 * Bs + p];
+            if (A.resume == 2) {
+              // its column and error bounds when it was handed on
+              pf_w0 = A.esc_pos[(size_t)p * J + s0];
+              pf_w1 = A.esc_pos[(size_t)p * J + s1];
+              pf_e0 = A.mig_err[(size_t)p * J + s0];
+              pf_e1 = A.mig_err[(size_t)p * J + s1];
+            } else {
+              pf_w0 = A.x0s[(size_t)s0 * Bs + p];
+              pf_w1 = A.x0s[(size_t)s1 * Bs + p];
+            }
           }
         }
       }
@@ -678,7 +750,7 @@ __global__ void __launch_bounds__(256) simpar32_kernel(SimArgs A) {
           const bool act = comp && s < D && ev == kE32None;
           float2 val = P[s * bd + tid];
           uint16_t vb = E[s * bd + tid];
-          float bx = 0.f, by = 0.f, ox = 0.f, oy = 0.f, h = 0.f, Eab = 0.f, rd = 0.f;
+          float bx = 0.f, by = 0.f, ox = 0.f, oy = 0.f, h = 0.f, Eab = 0.f, rd = 0.f, R = 0.f;
           bool bK = false, lock = false, deg = false;
           bool left = false;
           if (act) {
@@ -714,10 +786,13 @@ __global__ void __launch_bounds__(256) simpar32_kernel(SimArgs A) {
               const float d = d2 * rd;
               h = 0.5f * sK * rd;
               const float sensK = 4.f * d * fabsf(fmaf(0.5f, S + Dm, -d2));
-              const float kthr = fmaf(sensK, Eab, KB);
+              // as in the step-by-step pass: K's own evaluation error and the
+              // rounding of this placement
+              const float kthr = fmaf(sensK, Eab, fmaf(2.5f * uu, (S + d2) * (d2 + Dm), KB));
               bK = (fabsf(K) < kthr) | (d2 < CD);
+              R = fmaf(uu, fabsf(pa.x) + fabsf(pa.y), U2);
               const float A2 = 0.5f * (S - Dm) * rK;  // 2 ra rb / sqrt(K)
-              vb = bound_up(A2 * (Eab + fmaf(uu, fabsf(pa.x) + fabsf(pa.y), U2)));
+              vb = bound_up(A2 * (Eab + R));
               E[s * bd + tid] = vb;
             } else {
               deg = d2 <= DG;
@@ -731,7 +806,7 @@ __global__ void __launch_bounds__(256) simpar32_kernel(SimArgs A) {
             const float sg = fmaf(qx - bx, ox, (qy - by) * oy);
             const bool rule_left = sg >= 0.f;
             if ((MODE & 1) == 0) {
-              const float mthr = fmaf(Eab, fmaf(TS, rd, 1.f), EB + Ep);
+              const float mthr = fmaf(Eab, fmaf(TS, rd, 1.f), EB + Ep + R);
               const bool band = bK | (!orient && fabsf(sg) < mthr * h);
               ev = band ? kE32Band : lock ? kE32Lock : (!orient && rule_left != left) ? kE32Side : kE32None;
             } else {
@@ -751,11 +826,16 @@ __global__ void __launch_bounds__(256) simpar32_kernel(SimArgs A) {
       if (r + kSeg32 < mD) Cn[r + kSeg32] = make_float4(pf_q1.S, pf_q1.Dm, pf_q1.Kc, __uint_as_float(pf_q1.slots));
       if (r < mn) PN[r] = pf_w0;
       if (r + kSeg32 < mn) PN[r + kSeg32] = pf_w1;
+      if (A.resume == 2) {
+        if (r < mn) EN[r] = pf_e0;
+        if (r + kSeg32 < mn) EN[r + kSeg32] = pf_e1;
+      }
       CFN[r] = pf_cf;
       if (r == 0) {
         MCN[0] = (int)pf_meta;
         MCN[1] = pf_c;
         MCN[2] = pf_p;
+        MCN[3] = pf_t0;
       }
       in_flight = false;
       has_staged = true;
@@ -821,7 +901,7 @@ __global__ void __launch_bounds__(256) simpar32_kernel(SimArgs A) {
             e.pad = 0;
             A.esc[esc_i] = e;
           }
-          esc_i = atomicAdd(&A.counters[kCntEsc], 1);  // read at the next hand-over or at the end
+          esc_i = atomicAdd(A.esc_cnt, 1);  // read at the next hand-over or at the end
           esc_pend = true;
           esc_item = item;
           esc_te = te;
@@ -895,7 +975,11 @@ int sim32_lds_bytes(int nslot, int waves, int T) {
 }
 
 hipError_t launch_sim32(const SimArgs& a, int mode, const LaunchCfg& cfg, hipStream_t st) {
-  return mode == 0 ? dispatch<0>(a, cfg, st) : dispatch<1>(a, cfg, st);
+  switch (mode) {
+    case 0: return dispatch<0>(a, cfg, st);
+    case 1: return dispatch<1>(a, cfg, st);
+    default: return dispatch<4>(a, cfg, st);
+  }
 }
 
 template <int MODE>
@@ -910,21 +994,24 @@ int occ_d(int d, int waves, int lds) {
 
 int sim32_blocks_per_cu(int J, int mode, int T, int waves, int lds) {
   const int d = sim32_dmax(J);
-  const int m = (mode ? 1 : 0) | (T > kTableLds ? 2 : 0);
+  // mode 4 (recording sides) only with escalation
+  const int m = (mode & 5) | (T > kTableLds ? 2 : 0);
   switch (m) {
     case 0: return occ_d<0>(d, waves, lds);
     case 1: return occ_d<1>(d, waves, lds);
     case 2: return occ_d<2>(d, waves, lds);
-    default: return occ_d<3>(d, waves, lds);
+    case 3: return occ_d<3>(d, waves, lds);
+    case 4: return occ_d<4>(d, waves, lds);
+    default: return occ_d<6>(d, waves, lds);
   }
 }
 
 hipError_t launch_sim32_par(const SimArgs& a, int mode, const LaunchCfg& cfg, hipStream_t st) {
-  return mode == 0 ? dispatch_par32<0>(a, cfg, st) : dispatch_par32<1>(a, cfg, st);
+  return (mode & 1) == 0 ? dispatch_par32<0>(a, cfg, st) : dispatch_par32<1>(a, cfg, st);
 }
 
 int sim32_par_blocks_per_cu(int J, int mode, int T, int waves) {
-  const int m = (mode ? 1 : 0) | (T > kTableLds ? 2 : 0);
+  const int m = (mode & 1) | (T > kTableLds ? 2 : 0);
   switch (m) {
     case 0: return occ_par32_d<0>(J, waves, T);
     case 1: return occ_par32_d<1>(J, waves, T);

@@ -115,10 +115,11 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
   // chunk after the first starts with the step before it, placed on the sides the
   // decision passes recorded there (forced) and not written.  The decision passes
   // record sb, the sides of the current step, every ck_len steps.
-  // (compiled into the FP64-precision instantiations only: the exact arithmetic's
-  // step-by-step decision pass records, its path pass reads)
-  constexpr bool REC = SRC == kFromPerm && EXACT;
-  constexpr bool CK = SRC == kFromPath && EXACT;
+  // (the decision passes of FP64 precision and the hand-over pass record, every
+  // path pass reads; with FP32 decisions the FP32 pass records the steps it
+  // decides)
+  constexpr bool REC = (SRC == kFromPerm && EXACT) || SRC == kFromEsc;
+  constexpr bool CK = SRC == kFromPath;
   const bool chunked = CK && A.side_ck != nullptr;
   const int ckn = chunked ? A.ck_n : 1;
   uint32_t sb = 0u, fbits = 0u;
@@ -363,7 +364,8 @@ __global__ void __launch_bounds__(256) sim64_kernel(SimArgs A) {
               const double bx = fma(al, dx, pa.x), by = fma(al, dy, pa.y);
               const double ox = -be * dy, oy = be * dx;
               const double sg = fma(pr.x - bx, ox, (pr.y - by) * oy);
-              const bool left = orient ? ((obits >> s) & 1u) != 0u : sg >= 0.0;
+              const bool left = (orient || forced) ? (((forced ? fbits : obits) >> s) & 1u) != 0u : sg >= 0.0;
+              if (REC) sb |= (left ? 1u : 0u) << s;
               const double sgn = left ? 1.0 : -1.0;
               P[s * bd + tid] = make_double2(fma(sgn, ox, bx), fma(sgn, oy, by));
             }
@@ -867,6 +869,11 @@ __global__ void __launch_bounds__(256) simpar64_kernel(SimArgs A) {
     const int f = segm ? __ffs(segm) - 1 : W;
     const int info = __shfl(ev | (ev_s << 8), seg0 + (f < W ? f : 0));
     const int kind = f < W ? (info & 0xFF) : kEvNone;
+    // the sides of each decided step that ends a chunk of a path row (lanes before
+    // the segment's first event), for the chunked path pass
+    if (SRC != kFromPath && A.side_ck != nullptr && comp && r > 0 && r < f && t + 1 < T &&
+        ((t + 1) & (kPathChunk - 1)) == 0)
+      A.side_ck[(size_t)cand * A.ck_n + (t + 1) / kPathChunk] = side;
     if (SRC == kFromPath && comp && r > 0 && r < f) {
       const double2 po = P[out_slot * bd + tid];
       if (A.path_f64)

@@ -9,6 +9,9 @@ workload (batch size, joint-count mix, step count) and the device:
   spread      FP32 waves start spread over the solve-order buckets or all at the top
   refill64    refill threshold of the FP64 passes
   deesc       FP64 steps after a hand-over before a candidate returns to FP32
+  drain32     once the work list is exhausted, FP32 waves with fewer active lanes
+              than this hand their candidates to the parallel-in-time pass (0: never)
+  sort_esc    the FP64 hand-over pass takes its queue ordered by hand-over step
 
 `autotune` runs the real pass sequence on the caller's batch, timing each
 candidate setting with the library's own HIP events, and searches coordinate by
@@ -32,9 +35,12 @@ SPACE: Dict[str, List[int]] = {
     "spread": [1, 0],
     "refill64": [8, 32],
     "deesc": [0, 8],
+    "drain32": [0, 16, 32],
+    "sort_esc": [0, 1],
 }
 
-DEFAULTS: Dict[str, int] = {"waves32": 4, "refill_min": 32, "chunk": 128, "spread": 1, "refill64": 32, "deesc": 0}
+DEFAULTS: Dict[str, int] = {"waves32": 4, "refill_min": 32, "chunk": 128, "spread": 1, "refill64": 32, "deesc": 0,
+                            "drain32": 0, "sort_esc": 0}
 
 
 def cache_path() -> str:
@@ -78,7 +84,7 @@ def coordinate_search(measure: Callable[[Dict[str, int]], float], space: Dict[st
 def apply(ctx, cfg: Dict[str, int]):
     cur = ctx.get_tuning()
     ctx.set_tuning(cfg.get("waves32", cur["waves32"]), cfg.get("refill_min", cur["refill_min"]), cur["waves64"])
-    for k in ("chunk", "spread", "refill64", "deesc"):
+    for k in ("chunk", "spread", "refill64", "deesc", "drain32", "sort_esc"):
         if k in cfg:
             ctx.set_option(k, cfg[k])
 
@@ -88,14 +94,16 @@ def current(ctx) -> Dict[str, int]:
 
 
 def autotune(ctx, batch, T: int = 200, precision: int = 0, space: Optional[Dict[str, List[int]]] = None,
-             reps: int = 2, use_cache: bool = True, path: Optional[str] = None) -> dict:
+             reps: int = 2, use_cache: bool = True, path: Optional[str] = None, write: int = 0,
+             cap: Optional[int] = None) -> dict:
     """Tunes `ctx` for `batch` (a DeviceBatch) and leaves the best setting applied.
-    Returns {"config", "ms", "measurements", "cached"}."""
+    Each setting is timed on the call the caller will make: the same precision,
+    write mode and row capacity.  Returns {"config", "ms", "measurements", "cached"}."""
     import torch
     space = space or SPACE
     dev = batch.n.device
     name = torch.cuda.get_device_name(dev)
-    key = cache_key(name, batch.J, batch.B, T, precision)
+    key = cache_key(name, batch.J, batch.B, T, precision) + f"|w={write}"
     path = path or cache_path()
     table = {}
     if use_cache and os.path.exists(path):
@@ -109,15 +117,16 @@ def autotune(ctx, batch, T: int = 200, precision: int = 0, space: Optional[Dict[
         apply(ctx, cfg)
         return {"config": cfg, "ms": table[key]["ms"], "measurements": 0, "cached": True, "key": key}
 
-    out = ctx.simulate(batch, T=T, precision=precision)     # workspace and tables outside the timing
+    kw = dict(T=T, precision=precision, write=write, cap=cap)
+    out = ctx.simulate(batch, **kw)     # workspace and tables outside the timing
 
     def measure(cfg):
         apply(ctx, cfg)
-        ctx.simulate(batch, T=T, precision=precision, out=out)
+        ctx.simulate(batch, out=out, **kw)
         ctx.profile(True)
         tot = []
         for _ in range(reps):
-            ctx.simulate(batch, T=T, precision=precision, out=out)
+            ctx.simulate(batch, out=out, **kw)
             tot.append(sum(ctx.last_timings().values()))
         ctx.profile(False)
         return min(tot)

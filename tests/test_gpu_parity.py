@@ -151,6 +151,100 @@ def test_parallel_in_time_fp64_passes(ctx, L):
     assert np.array_equal(z["path"], ref["path"], equal_nan=True)
 
 
+@pytest.mark.parametrize("name,B,seed", [("dyad_6_20", 40000, 23), ("dyad_skewed", 40000, 24),
+                                         ("fourbar_u", 8000, 25)])
+def test_drain_handed_to_parallel_pass(ctx, L, name, B, seed):
+    """Once the work list is exhausted, nearly empty waves of the step-by-step FP32
+    pass hand their candidates (columns, error bounds, next step) to the
+    parallel-in-time pass: every decision, hand-over step and path equals the
+    pass without the hand-off, in both FP32 precisions and whatever the
+    threshold."""
+    _say(f"[drain] {name} B={B}")
+    b = gen.workload(name, B, seed=seed)
+    db = L.to_device(b)
+    prev = ctx.get_option("drain32")
+    try:
+        for precision in (L.FP32_RECHECK, L.FP32_ONLY):
+            ctx.set_option("drain32", 0)
+            base = _np(ctx.simulate(db, T=200, precision=precision, write=L.WRITE_ALL))
+            for thr in (1, 16, 48, 65):
+                ctx.set_option("drain32", thr)
+                r = _np(ctx.simulate(db, T=200, precision=precision, write=L.WRITE_ALL))
+                for k in ("status", "fail_step", "esc_step"):
+                    diff = np.nonzero(r[k] != base[k])[0]
+                    assert diff.size == 0, (precision, thr, k, diff[:5])
+                assert np.array_equal(r["path"], base["path"], equal_nan=True), (precision, thr)
+            for T in (1, 15, 16, 17, 1500):   # short rotations, one segment pass, a global crank table
+                ctx.set_option("drain32", 0)
+                base = _np(ctx.simulate(db, T=T, precision=precision))
+                ctx.set_option("drain32", 65)
+                r = _np(ctx.simulate(db, T=T, precision=precision))
+                for k in ("status", "fail_step", "esc_step"):
+                    assert np.array_equal(r[k], base[k]), (precision, T, k)
+    finally:
+        ctx.set_option("drain32", prev)
+
+
+@pytest.mark.parametrize("name,B,seed,T", [("dyad_6_20", 30000, 29, 200), ("dyad_skewed", 30000, 30, 200),
+                                           ("fourbar_u", 6000, 31, 200), ("dyad_4_20", 10000, 32, 77),
+                                           ("paper_8_20", 10000, 33, 1500)])
+def test_path_rows_in_chunks(ctx, L, name, B, seed, T):
+    """Path rows computed in 32-step chunks from the sides the FP32 pass and the
+    FP64 hand-over pass record at chunk ends equal rows computed whole, bit for
+    bit, with either hand-over pass and both write modes (FP32 decisions with
+    escalation; without escalation rows are always computed whole)."""
+    _say(f"[row chunks] {name} B={B} T={T}")
+    b = gen.workload(name, B, seed=seed)
+    db = L.to_device(b)
+    prev = (ctx.get_option("path_chunks"), ctx.get_option("par64"))
+    try:
+        for precision in (L.FP32_RECHECK, L.FP32_ONLY):
+            for par in (0, 1):
+                ctx.set_option("par64", par)
+                res = {}
+                for ck in (0, 1):
+                    ctx.set_option("path_chunks", ck)
+                    res[ck] = _np(ctx.simulate(db, T=T, precision=precision, write=L.WRITE_ALL, path_dtype=L.F64))
+                for k in ("status", "fail_step", "esc_step"):
+                    assert np.array_equal(res[0][k], res[1][k]), (precision, par, k)
+                diff = ~((res[0]["path"] == res[1]["path"]) | (np.isnan(res[0]["path"]) & np.isnan(res[1]["path"])))
+                assert not diff.any(), (precision, par, np.nonzero(diff.any(axis=(1, 2)))[0][:5])
+            ctx.set_option("path_chunks", 1)
+            v = _np(ctx.simulate(db, T=T, precision=precision, write=L.WRITE_VALID, cap=B))
+            k = int(v["n_written"][0])
+            assert np.array_equal(v["path"][:k], res[0]["path"][v["path_index"][:k]].astype(np.float32),
+                                  equal_nan=True)
+    finally:
+        ctx.set_option("path_chunks", prev[0])
+        ctx.set_option("par64", prev[1])
+
+
+def test_handover_queue_order(ctx, L):
+    """The FP64 hand-over pass takes its queue as handed over or ordered by
+    hand-over step: the same decisions and paths either way (and with the
+    step-by-step or parallel-in-time hand-over pass)."""
+    _say("[hand-over order]")
+    b = gen.workload("dyad_6_20", 40000, seed=28)
+    db = L.to_device(b)
+    prev = (ctx.get_option("sort_esc"), ctx.get_option("par64"))
+    res = {}
+    try:
+        for sort in (0, 1):
+            for par in (0, 1):
+                ctx.set_option("sort_esc", sort)
+                ctx.set_option("par64", par)
+                res[sort, par] = _np(ctx.simulate(db, T=200, write=L.WRITE_ALL))
+    finally:
+        ctx.set_option("sort_esc", prev[0])
+        ctx.set_option("par64", prev[1])
+    a = res[0, 1]
+    assert (a["esc_step"] >= 0).sum() > 1000
+    for key, z in res.items():
+        for k in ("status", "fail_step", "esc_step"):
+            assert np.array_equal(a[k], z[k]), (key, k)
+        assert np.array_equal(a["path"], z["path"], equal_nan=True), key
+
+
 @pytest.mark.parametrize("precision", [0, 2])
 def test_parallel_in_time_fp32_pass(ctx, L, precision):
     """The FP32 pass computed parallel in time takes every decision of the
@@ -281,6 +375,25 @@ def test_fp32_recheck_parity(ctx, L, name, B, seed):
     _say(f"[fp32r] {name} B={B}")
     b = gen.workload(name, B, seed=seed)
     _fp32_parity(ctx, L, b, label=name)
+
+
+def test_fp32_recheck_narrow_bands(ctx, L):
+    """Bands far below the defaults (eps_disc = 1e-9, no branch band): the FP32
+    pass may then take a decision in FP32 only where its tracked error bound,
+    including the rounding of the discriminant and of the placement themselves,
+    keeps it away from the threshold; everything outside these bands must equal
+    the oracle."""
+    _say("[fp32r narrow bands]")
+    b = gen.Batch.concat([gen.workload("dyad_6_20", 20000, seed=26), gen.workload("fourbar_u", 4000, seed=27)])
+    r = _np(ctx.simulate(L.to_device(b), T=200, precision=L.FP32_RECHECK, eps_disc=1e-9, eps_branch=0.0))
+    ref = oracle.simulate(b, T=200, margins=True, nthreads=NTH)
+    ib = oracle.in_band(ref["margins"], eps_disc=1e-9, eps_branch=0.0)
+    clear = ~ib
+    bad = clear & ((r["status"] != ref["status"]) | (r["fail_step"] != ref["fail_step"]))
+    _say(f"   out-of-band {clear.sum()} mismatches {bad.sum()}; in-band {ib.sum()}; "
+         f"handed to FP64 {(r['esc_step'] >= 0).mean():.3%}")
+    assert ib.mean() < 0.01
+    assert bad.sum() == 0, np.nonzero(bad)[0][:10]
 
 
 def test_fp32_recheck_parity_exact_handover(ctx, L):
