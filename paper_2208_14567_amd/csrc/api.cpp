@@ -767,8 +767,10 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
     LaunchCfg c32;
     c32.waves = ctx->waves32;
     c32.refill_min = ctx->refill_min;
-    // mode bit 0: no escalation; bit 2: the pass records the sides at chunk ends
-    const int mode = (opts->precision == LINKS_FP32_ONLY ? 1 : 0) | (chunks ? 4 : 0);
+    // mode bit 0: no escalation; bit 2: the pass records the sides at chunk ends;
+    // bit 3: the orientation branch rule
+    const int mode = (opts->precision == LINKS_FP32_ONLY ? 1 : 0) | (chunks ? 4 : 0) |
+                     (opts->branch == LINKS_BRANCH_ORIENTATION ? 8 : 0);
     if (ctx->par32 && ctx->deesc == 0) {
       c32.grid = grid_for(ctx, "par32", sim32_par_blocks_per_cu(J, mode, T, c32.waves));
       HIP_CHECK(launch_sim32_par(sa, mode, c32, st));

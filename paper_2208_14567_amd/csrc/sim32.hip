@@ -69,7 +69,7 @@ sim32_kernel(SimArgs A) {
   // a failure or hand-over stays in t until the results are written
   int fin = 0;
   int fcand = 0;
-  const bool orient = A.branch != 0;  // sides fixed at the start (else continuity)
+  constexpr bool orient = (MODE & 8) != 0;  // sides fixed at the start (else continuity)
   uint32_t obits = 0u;                // starting side of each placed joint
   int dmax_w = 0;  // largest solve order among the wave's lanes (uniform)
   float cS[DMAX], cDm[DMAX], cKc[DMAX];
@@ -978,7 +978,10 @@ hipError_t launch_sim32(const SimArgs& a, int mode, const LaunchCfg& cfg, hipStr
   switch (mode) {
     case 0: return dispatch<0>(a, cfg, st);
     case 1: return dispatch<1>(a, cfg, st);
-    default: return dispatch<4>(a, cfg, st);
+    case 4: return dispatch<4>(a, cfg, st);
+    case 8: return dispatch<8>(a, cfg, st);
+    case 9: return dispatch<9>(a, cfg, st);
+    default: return dispatch<12>(a, cfg, st);
   }
 }
 
@@ -995,14 +998,20 @@ int occ_d(int d, int waves, int lds) {
 int sim32_blocks_per_cu(int J, int mode, int T, int waves, int lds) {
   const int d = sim32_dmax(J);
   // mode 4 (recording sides) only with escalation
-  const int m = (mode & 5) | (T > kTableLds ? 2 : 0);
+  const int m = (mode & 13) | (T > kTableLds ? 2 : 0);
   switch (m) {
     case 0: return occ_d<0>(d, waves, lds);
     case 1: return occ_d<1>(d, waves, lds);
     case 2: return occ_d<2>(d, waves, lds);
     case 3: return occ_d<3>(d, waves, lds);
     case 4: return occ_d<4>(d, waves, lds);
-    default: return occ_d<6>(d, waves, lds);
+    case 6: return occ_d<6>(d, waves, lds);
+    case 8: return occ_d<8>(d, waves, lds);
+    case 9: return occ_d<9>(d, waves, lds);
+    case 10: return occ_d<10>(d, waves, lds);
+    case 11: return occ_d<11>(d, waves, lds);
+    case 12: return occ_d<12>(d, waves, lds);
+    default: return occ_d<14>(d, waves, lds);
   }
 }
 
