@@ -208,6 +208,34 @@ int links_simulate(links_ctx* ctx, const links_batch* batch, const links_sim_opt
 int links_simulate_noalloc(links_ctx* ctx, const links_batch* batch, const links_sim_opts* opts,
                            links_sim_out* out, void* stream);
 
+/* Serving support (no operation of the paper: the batching step of a serving
+ * loop that runs the simulation of the Methodology over requests of any size).
+ * Gathers into one batch the candidates of several requests,
+ * each stored in a byte buffer at its own joint stride, so that a request takes
+ * the device memory of its own layout.  A request block of `size` candidates at
+ * stride J (1..32) holds, each part starting 16-byte aligned from the block's
+ * start (itself 16-byte aligned in buf): x0 [size][J][2] f64, adj [size][J]
+ * u32, fixed [size] u32, n [size] u8, motor [size][2] u8.  Piece p fills rows
+ * dst[p] .. dst[p+1]-1 (the last piece up to `count`) of the output batch with
+ * candidates first[p], first[p]+1, ... of its request; pieces are in ascending
+ * dst from 0.  Rows count .. out->B-1 get n = 0 (BAD_MECH, never simulated).
+ * adj words and x0 pairs beyond a request's stride are zero.  buf, pieces and
+ * the output arrays are device pointers (out->x0 as f64), owned by the caller;
+ * the call is asynchronous on `stream`.  Pieces are device data and are not
+ * checked on the host: each must describe a block inside buf; a row whose piece
+ * has J outside [1, out->J] or a candidate index outside [0, size) is left
+ * empty (n = 0).  Errors: LINKS_ERR_ARG for NULL arrays, count outside
+ * [0, out->B], npieces < 1 with count > 0, or out->J outside [1, 32]. */
+typedef struct {
+  int64_t src;   /* byte offset of the request's block in buf */
+  int32_t dst;   /* first output row of the piece */
+  int32_t first; /* index within the request of the piece's first candidate */
+  int32_t size;  /* candidates in the request's block */
+  int32_t J;     /* the request's stride */
+} links_piece;
+int links_gather(links_ctx* ctx, const uint8_t* buf, const links_piece* pieces, int32_t npieces, int32_t count,
+                 const links_batch* out, void* stream);
+
 /* Launch parameters of the simulation passes (chosen by the autotuner in the
  * Python layer, or set by hand): waves32 / waves64 = wavefronts per workgroup of
  * the FP32 / FP64 pass (1..4); refill_min = idle lanes a wave waits for before it

@@ -1016,6 +1016,23 @@ int links_graph_create(links_ctx* ctx, const links_batch* batch, const links_sim
   return LINKS_OK;
 }
 
+int links_gather(links_ctx* ctx, const uint8_t* buf, const links_piece* pieces, int32_t npieces, int32_t count,
+                 const links_batch* out, void* stream) {
+  if (!ctx || !out) return fail(LINKS_ERR_ARG, "ctx or out is NULL");
+  if (out->J < 1 || out->J > links::kMaxJ) return fail(LINKS_ERR_ARG, "out J = %d outside [1, 32]", out->J);
+  if (count < 0 || count > out->B) return fail(LINKS_ERR_ARG, "count = %d outside [0, B = %d]", count, out->B);
+  if (count > 0 && (npieces < 1 || !buf || !pieces)) return fail(LINKS_ERR_ARG, "no pieces for %d rows", count);
+  if (out->B > 0 && (!out->n || !out->adj || !out->fixed || !out->motor || !out->x0))
+    return fail(LINKS_ERR_ARG, "output batch has a NULL array (x0 must be f64)");
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  HIP_CHECK(links::launch_gather(buf, pieces, npieces, count, out->B, out->J, const_cast<uint8_t*>(out->n),
+                                 const_cast<uint32_t*>(out->adj), const_cast<uint32_t*>(out->fixed),
+                                 const_cast<uint8_t*>(out->motor), const_cast<double*>(out->x0),
+                                 (hipStream_t)stream));
+  return LINKS_OK;
+}
+
 int links_graph_launch(links_graph* graph, void* stream) {
   if (!graph || !graph->exec) return fail(LINKS_ERR_ARG, "graph is NULL");
   int rc = set_device(graph->ctx);

@@ -190,6 +190,11 @@ hipError_t launch_chamfer_merge(const ChamferArgs& a, uint64_t* running, int64_t
                                 hipStream_t st);
 hipError_t launch_chamfer_clear(uint64_t* running, int64_t n, hipStream_t st);
 
+// serving: the tick's batch gathered from request blocks of their own strides (serve.hip)
+hipError_t launch_gather(const uint8_t* buf, const links_piece* pieces, int32_t npieces, int32_t count,
+                         int32_t rows, int32_t J, uint8_t* n, uint32_t* adj, uint32_t* fixed, uint8_t* motor,
+                         double* x0, hipStream_t st);
+
 // set-up and entry of the allocation-free variant of links_simulate
 // (noalloc.hip, api.cpp)
 int noalloc_setup(int device);

@@ -33,6 +33,11 @@ P = ctypes.c_void_p
 i32 = ctypes.c_int32
 
 
+# links_piece of include/links.h
+PIECE_DTYPE = np.dtype([("src", np.int64), ("dst", np.int32), ("first", np.int32), ("size", np.int32),
+                        ("J", np.int32)], align=True)
+
+
 class Batch(ctypes.Structure):
     _fields_ = [("B", i32), ("J", i32), ("n", P), ("adj", P), ("fixed", P), ("motor", P), ("x0", P),
                 ("x0_f32", P)]
@@ -54,7 +59,7 @@ EXPORTS = ["links_create", "links_destroy", "links_last_error", "links_version",
            "links_get_tuning", "links_set_option", "links_normalize_paths_n", "links_profile", "links_last_timings",
            "links_mean_timings", "links_simulate_noalloc",
            "links_graph_create", "links_graph_launch", "links_graph_destroy", "links_get_option",
-           "links_generate_dyads", "links_curate"]
+           "links_generate_dyads", "links_curate", "links_gather"]
 TIMING_PASSES = ["prep_count", "prep_fill", "fp32_pass", "fp64_pass", "compaction", "path_pass"]
 
 _lib = None
@@ -118,6 +123,8 @@ def load() -> ctypes.CDLL:
     L.links_graph_launch.restype = ctypes.c_int
     L.links_graph_destroy.argtypes = [P]
     L.links_graph_destroy.restype = None
+    L.links_gather.argtypes = [P, P, P, i32, i32, ctypes.POINTER(Batch), P]
+    L.links_gather.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -360,6 +367,15 @@ class Context:
         _check(load().links_graph_create(self._h, ctypes.byref(cb), ctypes.byref(opts), ctypes.byref(so),
                                          ctypes.byref(g)), "links_graph_create")
         return Graph(g, self, b, res)
+
+    def gather(self, buf: torch.Tensor, pieces: torch.Tensor, npieces: int, count: int, out: DeviceBatch,
+               stream=None):
+        """Fills rows 0 .. count-1 of ``out`` (f64 x0) from request blocks in the byte
+        buffer ``buf`` as described by ``npieces`` links_piece records in the device
+        tensor ``pieces`` (PIECE_DTYPE bytes); rows count .. out.B-1 get n = 0."""
+        cb = out.cstruct()
+        _check(load().links_gather(self._h, _ptr(buf), _ptr(pieces), int(npieces), int(count), ctypes.byref(cb),
+                                   _stream(stream)), "links_gather")
 
     # ------------------------------------------------------------------ normalisation
     def normalize_paths(self, paths: torch.Tensor, mode: int = NORM_PCA, out: Optional[torch.Tensor] = None,
