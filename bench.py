@@ -576,6 +576,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch parameters")
     ap.add_argument("--no-pipeline", action="store_true", help="skip the two-stream pipelined leg")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the secondary configurations (10k four-bars, 4M skewed joint counts)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--chunks", type=int, default=25, help="cfg5: chunks of 4M candidates")
     ap.add_argument("--bank", type=int, default=10_000_000, help="retrieval: bank paths")
@@ -783,6 +785,19 @@ def main():
 
     e2e = end_to_end(L, ctx, host, dev, T)
 
+    # the secondary configurations in the same record: 10k four-bars against the
+    # oracle, and 4M skewed joint counts with a sampled oracle check
+    secondary = None
+    if not args.no_secondary:
+        import copy
+        secondary = {}
+        for name in ("cfg1", "cfg3"):
+            a2 = copy.copy(args)
+            a2.config = name
+            t0 = time.time()
+            secondary[name] = other_config(a2, L, gen)
+            log(f"{name}: {secondary[name]['value']:.3e} sims/s ({time.time() - t0:.1f}s)")
+
     res = {
         "metric": METRIC,
         "value": B / sec32,
@@ -812,6 +827,7 @@ def main():
         "pipelined": pipelined,
         "serving": serving,
         "end_to_end": e2e,
+        "secondary": secondary,
         "stats": stats,
     }
     if args.copy_probe_mib > 0:

@@ -27,6 +27,9 @@ struct CandMeta {
   uint8_t flags;     // kFlag*
 };
 
+// relative rounding unit of an FP32 placement: four units of 2^-24
+constexpr float kRoundUnit = 0x1p-22f;
+
 // FP32 constants of one candidate (thresholds are already scaled)
 struct CandF32 {
   float px, py;  // pivot
@@ -37,7 +40,7 @@ struct CandF32 {
   float EB;      // escalation band on the branch distance: eps_branch scale
   float U2;      // rounding of one placement relative to the link lengths: u 2 scale
   float TS;      // 2 scale, a bound on 2 ra in the branch error term
-  float u;       // relative rounding unit of a placement
+  float u;       // relative rounding unit of a placement (kRoundUnit)
   float DG;      // degenerate threshold 1e-12 scale^2 (FP32-only mode)
   uint32_t side; // bit s: placed joint s starts left of its parents' line a->b
   float pad[3];

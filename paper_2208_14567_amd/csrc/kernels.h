@@ -65,8 +65,8 @@ struct PrepArgs {
   // sorting by solve-order length (records are written at the sorted position)
   int32_t Bs;            // stride of the per-entry record arrays
   uint8_t* dlen;         // [B] solve-order length, 0xFF when not simulated
-  int32_t* block_hist;   // [blocks][32]
-  int32_t* block_off;    // [blocks][32]
+  int32_t* block_hist;   // [32][blocks]: candidates of each solve-order length per count workgroup
+  int32_t* block_off;    // [32][blocks]: their exclusive prefix within the bucket
   int32_t* perm;         // [B] candidate at each sorted position
   double* scale_ws;      // [B] longest link of each pending candidate (count -> fill)
   int16_t* movable_ws;   // [B] its links not between two fixed joints (count -> fill)

@@ -267,6 +267,68 @@ __device__ StagedRow stage_rows(const PrepArgs& A, unsigned char* smem) {
   return r;
 }
 
+// The same copy in parts, for the register-resident count pass: the adjacency
+// rows ([J][64] u32), then kPosPart joints of the positions at a time ([2 kPosPart][64]
+// f64), each part through the same LDS buffer, so that a workgroup holds 8 KB of
+// LDS rather than 20 J bytes per lane and more workgroups share a CU.
+constexpr int kPosPart = 8;
+
+__host__ __device__ inline size_t parts_bytes(int J) {
+  const size_t a = (size_t)J * kSortBlock * 4, x = (size_t)kPosPart * kSortBlock * 16;
+  return a > x ? a : x;
+}
+
+__device__ void stage_adj(const PrepArgs& A, uint32_t* adj_l) {
+  const int J = A.J;
+  const int tid = threadIdx.x;
+  const int c0 = blockIdx.x * kSortBlock;
+  const int nc = min(kSortBlock, A.B - c0);
+  const uint32_t* ag = A.adj + (size_t)c0 * J;
+  const int total = nc * J;
+  for (int e0 = tid; e0 < total; e0 += kStageUnroll * kSortBlock) {
+    uint32_t av[kStageUnroll];
+#pragma unroll
+    for (int u = 0; u < kStageUnroll; ++u) av[u] = ag[min(e0 + u * kSortBlock, total - 1)];
+#pragma unroll
+    for (int u = 0; u < kStageUnroll; ++u) {
+      const int e = e0 + u * kSortBlock;
+      if (e < total) {
+        const int cand = e / J, i = e - cand * J;
+        adj_l[i * kSortBlock + cand] = av[u];
+      }
+    }
+  }
+}
+
+// joints j0 .. j0 + nj - 1 (nj <= kPosPart) of every candidate of the workgroup
+__device__ void stage_pos_part(const PrepArgs& A, double* x_l, int j0, int nj) {
+  const int J = A.J;
+  const int tid = threadIdx.x;
+  const int c0 = blockIdx.x * kSortBlock;
+  const int nc = min(kSortBlock, A.B - c0);
+  const double2* xg = reinterpret_cast<const double2*>(A.x0 + (size_t)c0 * J * 2);
+  const int total = nc * nj;
+  constexpr int U = kStageUnroll / 2;  // the positions of earlier parts are held in registers meanwhile
+  for (int e0 = tid; e0 < total; e0 += U * kSortBlock) {
+    double2 xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = min(e0 + u * kSortBlock, total - 1);
+      const int cand = e / nj, i = e - cand * nj;
+      xv[u] = xg[(size_t)cand * J + j0 + i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * kSortBlock;
+      if (e < total) {
+        const int cand = e / nj, i = e - cand * nj;
+        x_l[(2 * i) * kSortBlock + cand] = xv[u].x;
+        x_l[(2 * i + 1) * kSortBlock + cand] = xv[u].y;
+      }
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kPrepBlock) solve_order_kernel(PrepArgs A) {
   __shared__ uint32_t ord_l[kMaxJ * kPrepBlock];
   __shared__ uint8_t idx_l[kMaxJ * kPrepBlock];
@@ -313,11 +375,47 @@ __global__ void __launch_bounds__(kSortBlock) count_kernel(PrepArgs A) {
   const uint32_t fixed = in ? A.fixed[c] : 0u;
   const int pivot = in ? A.motor[2 * c] : 0, tip = in ? A.motor[2 * c + 1] : 0;
   const bool prev_rejected = in && A.pre_ratio > 0 && A.status[c] != 0;
-  const StagedRow row = stage_rows(A, smem);
   const int J = A.J;
   uint32_t R[JM];
+  double X[JM], Y[JM];
+  StagedRow row;  // above 24 joints: rows and positions read from LDS
+  row.adj = nullptr;
+  row.x0 = nullptr;
+  if (JM < 32) {
+    // rows, then the positions a part at a time, into registers
+    uint32_t* adj_l = reinterpret_cast<uint32_t*>(smem);
+    double* x_l = reinterpret_cast<double*>(smem);
+    stage_adj(A, adj_l);
+    __syncthreads();
 #pragma unroll
-  for (int i = 0; i < JM; i++) R[i] = i < J ? row.a(i) : 0u;
+    for (int i = 0; i < JM; i++) R[i] = i < J ? adj_l[i * kSortBlock + tid] : 0u;
+#pragma unroll
+    for (int j0 = 0; j0 < JM; j0 += kPosPart) {
+      if (j0 < J) {
+        const int nj = min(kPosPart, J - j0);
+        __syncthreads();  // the buffer's previous contents have been read
+        stage_pos_part(A, x_l, j0, nj);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPosPart; k++) {
+          const int i = j0 + k;
+          if (i < JM) {
+            const bool have = i < J && i < n;
+            X[i] = have ? x_l[(2 * k) * kSortBlock + tid] : 0.0;
+            Y[i] = have ? x_l[(2 * k + 1) * kSortBlock + tid] : 0.0;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < kPosPart; k++)
+          if (j0 + k < JM) X[j0 + k] = Y[j0 + k] = 0.0;
+      }
+    }
+  } else {
+    row = stage_rows(A, smem);
+#pragma unroll
+    for (int i = 0; i < JM; i++) R[i] = i < J ? row.a(i) : 0u;
+  }
   int dl = 0xFF;
   if (prev_rejected) {
     // rejected by the low-fidelity pass: keep its decision, on the fine grid
@@ -328,8 +426,7 @@ __global__ void __launch_bounds__(kSortBlock) count_kernel(PrepArgs A) {
   }
   if (in && !prev_rejected) {
     // the decisions do not depend on one another's order: integer ones first,
-    // then the positions are read for the geometry.  Above 24 joints the rows
-    // and positions no longer fit in registers and are read from LDS.
+    // then the positions for the geometry
     bool ok = JM < 32 ? reg_structure_ok<JM>(J, n, R, fixed, pivot, tip) : structure_ok(J, n, row, fixed, pivot, tip);
     int nd = 0;
     bool complete = false;
@@ -339,12 +436,6 @@ __global__ void __launch_bounds__(kSortBlock) count_kernel(PrepArgs A) {
     if (ok && JM == 32) {
       ok = geometry_ok(n, row, fixed, &scale, &movable);
     } else if (ok) {
-      double X[JM], Y[JM];
-#pragma unroll
-      for (int i = 0; i < JM; i++) {
-        X[i] = i < n ? row.x(i) : 0.0;
-        Y[i] = i < n ? row.y(i) : 0.0;
-      }
       ok = reg_geometry_ok<JM>(n, R, X, Y, fixed, A.len2_min, &scale, &movable);
     }
     uint8_t st = !ok ? 5 : (complete ? kPending : 4);
@@ -360,36 +451,45 @@ __global__ void __launch_bounds__(kSortBlock) count_kernel(PrepArgs A) {
       if (A.esc_step) A.esc_step[c] = -1;
     }
   }
-  // histogram of D over the workgroup (one wave)
+  // histogram of D over the workgroup (one wave), stored by bucket: [32][blocks]
   for (int d = 0; d < kMaxJ; d++) {
     const int k = __popcll(__ballot(dl == d));
-    if (tid == d) A.block_hist[(size_t)blockIdx.x * kMaxJ + d] = k;
+    if (tid == d) A.block_hist[(size_t)d * gridDim.x + blockIdx.x] = k;
   }
 }
 
-// pass 2: exclusive scan of every bucket's per-workgroup counts (one workgroup per D)
+// pass 2: exclusive scan of every bucket's per-workgroup counts (one workgroup per
+// D, reading the bucket's row of [32][blocks] a tile of 1024 at a time): a scan
+// within each wave, then over the 16 wave totals
 __global__ void __launch_bounds__(1024) offsets_kernel(int32_t nblocks, const int32_t* block_hist,
                                                         int32_t* block_off, int32_t* counters) {
-  __shared__ int32_t s[1024];
-  __shared__ int32_t carry;
+  __shared__ int32_t wsum[16];
   const int d = blockIdx.x;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
+  const int32_t* h = block_hist + (size_t)d * nblocks;
+  int32_t* o = block_off + (size_t)d * nblocks;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int carry = 0;
   for (int base = 0; base < nblocks; base += 1024) {
     const int i = base + threadIdx.x;
-    const int v = i < nblocks ? block_hist[(size_t)i * kMaxJ + d] : 0;
-    s[threadIdx.x] = v;
-    __syncthreads();
-    for (int w = 1; w < 1024; w <<= 1) {
-      const int add = threadIdx.x >= w ? s[threadIdx.x - w] : 0;
-      __syncthreads();
-      s[threadIdx.x] += add;
-      __syncthreads();
+    const int v = i < nblocks ? h[i] : 0;
+    int x = v;  // inclusive scan within the wave
+#pragma unroll
+    for (int k = 1; k < kWave; k <<= 1) {
+      const int y = __shfl_up(x, k);
+      if (lane >= k) x += y;
     }
-    if (i < nblocks) block_off[(size_t)i * kMaxJ + d] = carry + s[threadIdx.x] - v;
+    if (lane == kWave - 1) wsum[w] = x;
     __syncthreads();
-    if (threadIdx.x == 1023) carry += s[1023];
-    __syncthreads();
+    int pre = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+      const int t = wsum[k];
+      pre += k < w ? t : 0;
+      tot += t;
+    }
+    if (i < nblocks) o[i] = carry + pre + x - v;
+    carry += tot;
+    __syncthreads();  // wsum is rewritten by the next tile
   }
   if (threadIdx.x == 0) counters[kCntHist + d] = carry;
 }
@@ -421,7 +521,7 @@ __global__ void __launch_bounds__(kSortBlock) rank_kernel(PrepArgs A) {
     if (myd == d) rank = __popcll(m & below);
   }
   if (myd == 0xFF) return;
-  const int p = A.counters[kCntOff + myd] + A.block_off[(size_t)blockIdx.x * kMaxJ + myd] + rank;
+  const int p = A.counters[kCntOff + myd] + A.block_off[(size_t)myd * gridDim.x + blockIdx.x] + rank;
   A.perm[p] = c;
 }
 
@@ -431,8 +531,8 @@ __global__ void __launch_bounds__(kSortBlock) rank_kernel(PrepArgs A) {
 template <int JM>
 __global__ void __launch_bounds__(kSortBlock) fill_kernel(PrepArgs A) {
   extern __shared__ unsigned char smem[];
-  __shared__ uint32_t ord_l[kMaxJ * kSortBlock];
-  __shared__ uint8_t idx_l[kMaxJ * kSortBlock];
+  __shared__ uint32_t ord_l[JM * kSortBlock];
+  __shared__ uint8_t idx_l[JM * kSortBlock];
   const int tid = threadIdx.x;
   const int p = blockIdx.x * kSortBlock + tid;
   if (p >= A.counters[kCntItems]) return;
@@ -520,7 +620,7 @@ __global__ void __launch_bounds__(kSortBlock) fill_kernel(PrepArgs A) {
 
   // FP32 thresholds and error units: a computed position carries at most a few
   // units of FP32 rounding of its magnitude before amplification
-  const double u = 4.0 * 5.9604644775390625e-08;
+  const double u = (double)kRoundUnit;
   CandF32 cf;
   cf.px = (float)px;
   cf.py = (float)py;
@@ -761,7 +861,8 @@ size_t fill_bytes(int J) { return (size_t)J * kSortBlock * 16; }
 
 template <int JM>
 void count_one(const PrepArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(count_kernel<JM>, dim3(prep_blocks(a.B)), dim3(kSortBlock), staged_bytes(a.J), st, a);
+  hipLaunchKernelGGL(count_kernel<JM>, dim3(prep_blocks(a.B)), dim3(kSortBlock),
+                     JM < 32 ? parts_bytes(a.J) : staged_bytes(a.J), st, a);
 }
 
 hipError_t launch_prep_count(const PrepArgs& a, hipStream_t st) {

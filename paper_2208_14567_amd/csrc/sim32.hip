@@ -60,7 +60,8 @@ sim32_kernel(SimArgs A) {
   const int Bs = A.Bs;
   int cand = -1, item = 0, t = 0, D = 0, n = 0;
   float px = 0.f, py = 0.f, vx = 0.f, vy = 0.f, U = 0.f, KB = 0.f, CD = 0.f, EB = 0.f;
-  float U2 = 0.f, TS = 0.f, uu = 0.f, DG = 0.f;
+  float U2 = 0.f, TS = 0.f, DG = 0.f;
+  constexpr float uu = kRoundUnit;  // the same for every candidate
   bool force64 = false;
   // A finished candidate's results are written later, for all finished lanes of
   // the wave together (at the next refill or when the wave leaves): its lane is
@@ -305,7 +306,6 @@ sim32_kernel(SimArgs A) {
           EB = f.EB;
           U2 = f.U2;
           TS = f.TS;
-          uu = f.u;
           DG = f.DG;
           obits = f.side;
 #pragma unroll
