@@ -275,14 +275,22 @@ def stream_config(args, L, gen, oracle, tune, dev, threads):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     total = nch * CH
-    # parity: the first 20,000 candidates of three chunks against the oracle
+    # CPU baseline: the oracle on the first 20,000 candidates of three chunks,
+    # with the GPU's agreement on them
     par = {}
+    t_or, n_or = 0.0, 0
     for i, (st_, fs_) in sorted(sample.items()):
         hb = gen.dyad_batch(20000, seed, gen.n_uniform(6, 20), 20, first=i * CH)
+        t1 = time.perf_counter()
         ref = oracle.simulate(hb, T=T, margins=True, nthreads=threads)
+        t_or += time.perf_counter() - t1
+        n_or += hb.B
         clear = ~oracle.in_band(ref["margins"])
         eq = (st_.numpy() == ref["status"]) & (fs_.numpy() == ref["fail_step"])
         par[f"chunk_{i}"] = {"out_of_band": int(clear.sum()), "out_of_band_equal": float(eq[clear].mean())}
+    cpu = {"value": n_or / t_or, "unit": "sims/s", "cores": threads, "kind": "oracle",
+           "sample": f"first 20,000 candidates of chunks {sorted(sample)}, FP64 with margins",
+           "gpu_agreement": par}
     return {"metric": "mechanism sims/sec (200 steps), streamed, end to end", "unit": "sims/s",
             "value": total / wall, "wall_s": wall,
             "config": {"workload": f"{total} dyad-built candidates (n~U{{6..20}}, x0~U[0,1)^2, seed 5) generated on "
@@ -291,7 +299,7 @@ def stream_config(args, L, gen, oracle, tune, dev, threads):
                        "candidates": total, "chunks": nch, "tuning": tuned["config"]},
             "valid_paths": stats["valid"], "valid_fraction": stats["valid"] / total,
             "paths_dropped_over_cap": stats["dropped"], "d2h_bytes": stats["d2h_bytes"],
-            "d2h_GBps": stats["d2h_bytes"] / wall / 1e9, "sample_parity": par}
+            "d2h_GBps": stats["d2h_bytes"] / wall / 1e9, "cpu_baseline": cpu}
 
 
 def next_config(args, L, gen):
@@ -317,16 +325,20 @@ def next_config(args, L, gen):
                    "samples_per_valid": (per_n / valid) if valid else None,
                    "wasted": 1.0 - valid / per_n}
             if n in (6, 12, 20):
-                # the first 20,000 against the oracle, decisions outside the bands
+                # CPU baseline: the oracle on the first 20,000 (the same draws), with
+                # the GPU's agreement on the decisions outside the bands
                 k = 20_000
                 sub = gen.dyad_batch(k, 900 + n, gen.n_uniform(n, n), J=20, paper_mode=paper,
-                                     rules=rules)  # the same draws
+                                     rules=rules)
                 if paper:
                     sub = gen.standardize_paper(sub)  # as the device generator places pivot and tip
+                t1 = time.perf_counter()
                 ref = oracle.simulate(sub, T=T, margins=True, nthreads=threads)
+                t_or = time.perf_counter() - t1
                 clear = ~oracle.in_band(ref["margins"])
-                row["oracle_sample"] = {"candidates": k, "out_of_band": int(clear.sum()),
-                                        "status_equal": float((st[:k][clear] == ref["status"][clear]).mean())}
+                row["cpu_baseline"] = {"value": k / t_or, "unit": "sims/s", "cores": threads, "kind": "oracle",
+                                       "sample": f"first {k} candidates", "out_of_band": int(clear.sum()),
+                                       "gpu_status_equal": float((st[:k][clear] == ref["status"][clear]).mean())}
             rows.append(row)
             name = ("paper_mode" if paper else "dyad") + ("_rules" if rules else "")
             log(f"{name} n={n}: {valid} valid of {per_n}")
@@ -377,6 +389,7 @@ def other_config(args, L, gen):
         res = {"metric": "four-bar sims/sec (200 steps)", "unit": "sims/s", "config": {
             "workload": "10,000 Grashof crank-rocker four-bars with a coupler point, x0~U[0,1)^2, T=200",
             "candidates": host.B, "T": T, "seed": 1}}
+        agree = {}
         for name, prec in (("gpu_fp64", L.FP64), ("gpu_fp32_recheck", L.FP32_RECHECK)):
             dt, passes, r = time_sim(ctx, db, reps=20, T=T, precision=prec, write=L.WRITE_ALL,
                                      path_dtype=L.F64 if prec == L.FP64 else L.F32)
@@ -388,13 +401,15 @@ def other_config(args, L, gen):
                               for c in range(host.B)])
             ok = (st == ref["status"]) & (fs == ref["fail_step"])
             err = np.nanmax(np.abs(path - ref["path"]), axis=(1, 2)) / scale
-            res[name] = {"value": host.B / dt, "ms": dt * 1e3, "passes_ms": passes,
-                         "status_equal": float(ok.mean()), "max_path_error_over_scale": float(np.nanmax(err)),
-                         "bit_exact_paths": bool(np.array_equal(np.nan_to_num(path, nan=7.0),
-                                                                np.nan_to_num(ref["path"], nan=7.0)))}
+            res[name] = {"value": host.B / dt, "ms": dt * 1e3, "passes_ms": passes}
+            agree[name] = {"status_equal": float(ok.mean()), "max_path_error_over_scale": float(np.nanmax(err)),
+                           "bit_exact_paths": bool(np.array_equal(np.nan_to_num(path, nan=7.0),
+                                                                  np.nan_to_num(ref["path"], nan=7.0)))}
         res["value"] = res["gpu_fp32_recheck"]["value"]
         res["valid_fraction"] = float((ref["status"] == 0).mean())
-        res["cpu_oracle"] = {"value": host.B / t_or, "cores": threads, "one_core": host.B / t_or1}
+        res["cpu_baseline"] = {"value": host.B / t_or, "unit": "sims/s", "cores": threads, "kind": "oracle",
+                               "sample": "all 10,000 four-bars, FP64 with paths", "one_core": host.B / t_or1,
+                               "gpu_agreement": agree}
         return res
     if args.config == "cfg1x":
         B = 10_000_000
@@ -427,9 +442,11 @@ def other_config(args, L, gen):
     tuned64 = tune.autotune(ctx64, db, T=T, precision=L.FP64, use_cache=False,
                             space={"chunk": tune.SPACE["chunk"], "refill64": [1, 8, 32]})
     dt64, passes64, r64 = time_sim(ctx64, db, reps=10, T=T, precision=L.FP64)
-    # parity on a sample the oracle computes
+    # CPU baseline: the oracle on a random sample, with the GPU's agreement on it
     idx = np.random.default_rng(0).choice(B, 20000, replace=False)
+    t1 = time.perf_counter()
     ref = oracle.simulate(host.take(idx), T=T, margins=True, nthreads=threads)
+    t_or = time.perf_counter() - t1
     clear = ~oracle.in_band(ref["margins"])
     fs = r["fail_step"].cpu().numpy()
     agree = (st[idx] == ref["status"]) & (fs[idx] == ref["fail_step"])
@@ -442,9 +459,12 @@ def other_config(args, L, gen):
                            "tuning": tuned64["config"]},
             "valid_fraction": float((st == 0).mean()),
             "escalated_fraction": float((r["esc_step"].cpu().numpy() >= 0).mean()),
-            "sample_parity": {"sample": int(idx.size), "out_of_band": int(clear.sum()),
-                              "out_of_band_equal": float(agree[clear].mean()),
-                              "in_band_equal": float(agree[~clear].mean()) if (~clear).any() else None}}
+            "cpu_baseline": {"value": idx.size / t_or, "unit": "sims/s", "cores": threads, "kind": "oracle",
+                             "sample": f"{idx.size} random candidates of the batch",
+                             "gpu_agreement": {"out_of_band": int(clear.sum()),
+                                               "out_of_band_equal": float(agree[clear].mean()),
+                                               "in_band_equal": float(agree[~clear].mean()) if (~clear).any()
+                                               else None}}}
 
 
 ALU_LANES = FP32_PEAK / 2        # FP32 lane operations per second (one FMA = 2 FLOP): 128 lanes x 256 CUs x 2.4 GHz
@@ -521,7 +541,8 @@ def retrieval_config(args, L, gen):
     rate = pairs / best_s
     achieved = rate * T * T
     peak = ALU_LANES / CHAMFER_OPS_PER_PAIR
-    # oracle: the returned answers and 300 sampled distances per query
+    # CPU baseline leg: the oracle's distances for the returned answers and 300
+    # sampled bank paths per query (agreement), and its rate on a bounded sample
     hb = bank.cpu().numpy() if P <= 2_000_000 else None
     qh = queries.cpu().numpy()
     bi, bd, fi, fd = (x.cpu().numpy() for x in (bidx, bdist, fidx, fdist))
@@ -552,9 +573,9 @@ def retrieval_config(args, L, gen):
             "first_dist": fd.tolist(), "best_idx": bi.tolist(), "best_dist": bd.tolist(),
             "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "point pairs/s",
                          "frac": achieved / peak, "ops_per_pair": CHAMFER_OPS_PER_PAIR},
-            "oracle_check": {"rows_checked": checked, "max_rel_err": max(errs)},
             "cpu_baseline": {"value": cpu_rate, "unit": "comparisons/s", "cores": 1, "kind": "oracle",
-                             "sample": f"1 query against {cpu_n} bank paths (numpy float64)"},
+                             "sample": f"1 query against {cpu_n} bank paths (numpy float64)",
+                             "gpu_agreement": {"rows_checked": checked, "max_rel_err": max(errs)}},
             "bank_build_s": build_s,
             "path_shapes": {"valid_paths_seen": shapes["valid"],
                             "arc_fraction": shapes["arc"] / max(shapes["valid"], 1),
