@@ -190,90 +190,31 @@ def stream_config(args, L, gen, oracle, tune, dev, threads):
     """cfg5: chunks of 4M dyad-built candidates (n ~ U{6..20}, seed 5) generated on
     the device, simulated (FP32 with FP64 escalation), valid coupler paths
     PCA-normalised on the device, and only the valid paths, their candidate
-    indices and transforms copied to pinned host memory.  Two contexts on two
-    streams alternate chunks, so one chunk's copies overlap the next chunk's
-    simulation."""
+    indices and transforms copied to pinned host memory (the package's Streamer:
+    two lanes alternate chunks, so one chunk's copies overlap the next chunk's
+    simulation)."""
     import torch
+    from paper_2208_14567_amd import stream as S
     CH, T, seed = 4_000_000, args.T, 5
     nch = args.chunks
     cap = 1_000_000
-    lanes = []
-    for _ in range(2):
-        ctx = L.Context(0)
-        st = torch.cuda.Stream(device=dev)
-        lane = {"ctx": ctx, "stream": st,
-                "batch": L.DeviceBatch(torch.empty(CH, dtype=torch.uint8, device=dev),
-                                       torch.empty((CH, 20), dtype=torch.int32, device=dev),
-                                       torch.empty(CH, dtype=torch.int32, device=dev),
-                                       torch.empty((CH, 2), dtype=torch.uint8, device=dev),
-                                       torch.empty((CH, 20, 2), dtype=torch.float64, device=dev)),
-                "out": {"status": torch.empty(CH, dtype=torch.uint8, device=dev),
-                        "fail_step": torch.empty(CH, dtype=torch.int16, device=dev),
-                        "esc_step": torch.empty(CH, dtype=torch.int16, device=dev),
-                        "path": torch.empty((cap, T, 2), dtype=torch.float32, device=dev),
-                        "path_index": torch.empty(cap, dtype=torch.int32, device=dev),
-                        "n_written": torch.empty(1, dtype=torch.int32, device=dev)},
-                "norm": torch.empty((cap, T, 2), dtype=torch.float32, device=dev),
-                "xform": torch.empty((cap, 5), dtype=torch.float32, device=dev),
-                "h_path": torch.empty((cap, T, 2), dtype=torch.float32).pin_memory(),
-                "h_index": torch.empty(cap, dtype=torch.int32).pin_memory(),
-                "h_xform": torch.empty((cap, 5), dtype=torch.float32).pin_memory(),
-                "h_count": torch.empty(1, dtype=torch.int32).pin_memory(),
-                "pending": None}
-        lanes.append(lane)
+    cfg = S.StreamConfig(seed=seed, chunks=nch, chunk=CH, T=T, cap=cap)
     # tune once on a generated chunk, then use the setting on both lanes
-    first = lanes[0]
-    first["ctx"].generate_dyads(CH, seed, first=0, out=first["batch"])
-    tuned = tune.autotune(first["ctx"], first["batch"], T=T, precision=L.FP32_RECHECK, use_cache=False,
-                          write=L.WRITE_VALID, cap=cap)
-    tune.apply(lanes[1]["ctx"], tuned["config"])
+    tctx = L.Context(0)
+    tb = tctx.generate_dyads(CH, seed, first=0)
+    tuned = tune.autotune(tctx, tb, T=T, precision=L.FP32_RECHECK, use_cache=False, write=L.WRITE_VALID, cap=cap)
+    del tb
+    streamer = S.Streamer(cfg, tuning=tuned["config"], keep_status=20000)
     sample_chunks = {0, nch // 2, nch - 1}
     sample = {}
-    stats = {"valid": 0, "dropped": 0, "d2h_bytes": 0}
 
-    def enqueue(lane, i):
-        with torch.cuda.stream(lane["stream"]):
-            c, s = lane["ctx"], lane["stream"]
-            c.generate_dyads(CH, seed, first=i * CH, out=lane["batch"], stream=s)
-            c.simulate(lane["batch"], T=T, write=L.WRITE_VALID, cap=cap, out=lane["out"], stream=s)
-            c.normalize_paths_n(lane["out"]["path"], lane["out"]["n_written"], L.NORM_PCA, out=lane["norm"],
-                                xform=lane["xform"], stream=s)
-            lane["h_count"].copy_(lane["out"]["n_written"], non_blocking=True)
-            ev = torch.cuda.Event()
-            ev.record(s)
-        lane["pending"] = (i, ev)
+    def inspect(c, status, fail_step):
+        if c in sample_chunks:
+            sample[c] = (status.copy(), fail_step.copy())
 
-    def drain(lane):
-        if lane["pending"] is None:
-            return
-        i, ev = lane["pending"]
-        ev.synchronize()
-        k = int(lane["h_count"][0])
-        kk = min(k, cap)
-        stats["valid"] += k
-        stats["dropped"] += k - kk
-        with torch.cuda.stream(lane["stream"]):
-            lane["h_path"][:kk].copy_(lane["norm"][:kk], non_blocking=True)
-            lane["h_index"][:kk].copy_(lane["out"]["path_index"][:kk], non_blocking=True)
-            lane["h_xform"][:kk].copy_(lane["xform"][:kk], non_blocking=True)
-            if i in sample_chunks:
-                sample[i] = (lane["out"]["status"][:20000].cpu(), lane["out"]["fail_step"][:20000].cpu())
-        stats["d2h_bytes"] += kk * (T * 8 + 4 + 20)
-        lane["pending"] = None
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(nch):
-        lane = lanes[i % 2]
-        drain(lane)                 # its previous chunk: count, then copies queued behind the next chunk's work
-        enqueue(lane, i)
-        drain_other = lanes[(i + 1) % 2]
-        if drain_other["pending"] is not None and drain_other["pending"][0] < i:
-            drain(drain_other)
-    for lane in lanes:
-        drain(lane)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    res = streamer.run(sink=None, inspect=inspect)
+    wall = res["wall_s"]
+    stats = res
     total = nch * CH
     # CPU baseline: the oracle on the first 20,000 candidates of three chunks,
     # with the GPU's agreement on them
@@ -286,7 +227,7 @@ def stream_config(args, L, gen, oracle, tune, dev, threads):
         t_or += time.perf_counter() - t1
         n_or += hb.B
         clear = ~oracle.in_band(ref["margins"])
-        eq = (st_.numpy() == ref["status"]) & (fs_.numpy() == ref["fail_step"])
+        eq = (st_ == ref["status"]) & (fs_ == ref["fail_step"])
         par[f"chunk_{i}"] = {"out_of_band": int(clear.sum()), "out_of_band_equal": float(eq[clear].mean())}
     cpu = {"value": n_or / t_or, "unit": "sims/s", "cores": threads, "kind": "oracle",
            "sample": f"first 20,000 candidates of chunks {sorted(sample)}, FP64 with margins",
