@@ -524,21 +524,31 @@ class Server:
             pass
 
 
-def run_stream(server: Server, requests: List, arrivals: np.ndarray) -> List[Request]:
+def run_stream(server: Server, requests: List, arrivals: np.ndarray, pause_gc: bool = True) -> List[Request]:
     """Submits requests[i] (a DeviceBatch or Packed) at arrivals[i] seconds after the
     start, polling the server in between; returns the finished requests in
-    submission order."""
-    t0 = time.perf_counter()
-    order = np.argsort(arrivals, kind="stable")
-    reqs: Dict[int, Request] = {}
-    i = 0
-    while i < len(order) or server.poll():
-        now = time.perf_counter() - t0
-        while i < len(order) and arrivals[order[i]] <= now:
-            j = order[i]
-            reqs[j] = server.submit(requests[j], arrival=t0 + float(arrivals[j]))
-            i += 1
-        server.poll()
+    submission order.  With pause_gc, Python's cyclic garbage collector is paused
+    while the loop runs (a collection pass over the loop's objects stalls the
+    scheduler for tens of milliseconds; reference counting still frees memory)."""
+    import gc
+    was = gc.isenabled()
+    if pause_gc:
+        gc.disable()
+    try:
+        t0 = time.perf_counter()
+        order = np.argsort(arrivals, kind="stable")
+        reqs: Dict[int, Request] = {}
+        i = 0
+        while i < len(order) or server.poll():
+            now = time.perf_counter() - t0
+            while i < len(order) and arrivals[order[i]] <= now:
+                j = order[i]
+                reqs[j] = server.submit(requests[j], arrival=t0 + float(arrivals[j]))
+                i += 1
+            server.poll()
+    finally:
+        if was:
+            gc.enable()
     return [reqs[j] for j in range(len(requests))]
 
 
