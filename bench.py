@@ -371,6 +371,41 @@ def other_config(args, L, gen):
                              "bytes_per_launch": wbytes}}
     if args.config == "cfg5":
         return stream_config(args, L, gen, oracle, tune, dev, threads)
+    if args.config == "cfg2_rules":
+        # the headline's shape with the paper's topology rules ("Generating Valid
+        # Topologies"): the same step, valid paths written, far fewer survivors
+        B = 1_000_000
+        ctx = L.Context(0)
+        # generated on the device (the host generator's candidates, bit for bit)
+        db = ctx.generate_dyads(B, 11, J=20, n_lo=6, n_hi=20, rules=True)
+        tuned = tune.autotune(ctx, db, T=T, precision=L.FP32_RECHECK, use_cache=False, write=L.WRITE_VALID, cap=B)
+        dt, passes, r = time_sim(ctx, db, reps=10, T=T, precision=L.FP32_RECHECK, write=L.WRITE_VALID, cap=B)
+        st = r["status"].cpu().numpy()
+        fs = r["fail_step"].cpu().numpy()
+        ctx64 = L.Context(0)
+        dt64, passes64, _ = time_sim(ctx64, db, reps=10, T=T, precision=L.FP64, write=L.WRITE_VALID, cap=B)
+        k = 20_000
+        sample = gen.dyad_batch(k, 11, gen.n_uniform(6, 20), 20, rules=True)  # the first k, on the host
+        t1 = time.perf_counter()
+        ref = oracle.simulate(sample, T=T, margins=True, nthreads=threads)
+        t_or = time.perf_counter() - t1
+        clear = ~oracle.in_band(ref["margins"])
+        agree = (st[:k] == ref["status"]) & (fs[:k] == ref["fail_step"])
+        return {"metric": "mechanism sims/sec (200 steps), topology rules", "unit": "sims/s", "value": B / dt,
+                "ms_per_step": dt * 1e3, "passes_ms": passes, "tuning": tuned["config"],
+                "config": {"workload": "1M dyad-built candidates with the paper's topology rules (last joint "
+                                       "depends on every joint and is linked to no fixed joint), n~U{6..20}, "
+                                       "x0~U[0,1)^2, T=200, FP32 with FP64 escalation, valid paths written",
+                           "candidates": B, "T": T, "seed": 11},
+                "fp64_plain": {"value": B / dt64, "ms_per_step": dt64 * 1e3, "passes_ms": passes64},
+                "valid_fraction": float((st == 0).mean()),
+                "escalated_fraction": float((r["esc_step"].cpu().numpy() >= 0).mean()),
+                "cpu_baseline": {"value": k / t_or, "unit": "sims/s", "cores": threads, "kind": "oracle",
+                                 "sample": f"first {k} candidates",
+                                 "gpu_agreement": {"out_of_band": int(clear.sum()),
+                                                   "out_of_band_equal": float(agree[clear].mean()),
+                                                   "in_band_equal": float(agree[~clear].mean()) if (~clear).any()
+                                                   else None}}}
     # cfg3: 4M skewed joint counts, autotuned
     B = 4_000_000
     host = gen.workload("dyad_skewed", B, seed=3)
@@ -539,15 +574,17 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch parameters")
     ap.add_argument("--no-pipeline", action="store_true", help="skip the two-stream pipelined leg")
     ap.add_argument("--no-secondary", action="store_true",
-                    help="skip the secondary configurations (10k four-bars, 4M skewed joint counts)")
+                    help="skip the secondary configurations (10k four-bars, 1M with the topology rules, "
+                         "4M skewed joint counts)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--chunks", type=int, default=25, help="cfg5: chunks of 4M candidates")
     ap.add_argument("--bank", type=int, default=10_000_000, help="retrieval: bank paths")
-    ap.add_argument("--config", choices=["cfg2", "cfg1", "cfg1x", "cfg3", "cfg5", "next", "retrieval"],
+    ap.add_argument("--config", choices=["cfg2", "cfg1", "cfg1x", "cfg2_rules", "cfg3", "cfg5", "next", "retrieval"],
                     default="cfg2",
                     help="cfg2: the headline (1M dyad-built, 6-20 joints); cfg1: 10k crank-rocker four-bars "
                          "(oracle, GPU FP64, GPU FP32+recheck); cfg1x: 10M four-bars writing every path "
-                         "(HBM-write roofline); cfg3: 4M skewed joint counts; cfg5: a stream of "
+                         "(HBM-write roofline); cfg2_rules: the headline's shape with the paper's topology "
+                         "rules; cfg3: 4M skewed joint counts; cfg5: a stream of "
                          "100M candidates generated on the device in 4M chunks, valid paths normalised "
                          "and copied to the host; next: samples per valid mechanism against the joint "
                          "count and the low-fidelity screen; retrieval: chamfer search over a bank of "
@@ -753,7 +790,7 @@ def main():
     if not args.no_secondary:
         import copy
         secondary = {}
-        for name in ("cfg1", "cfg3"):
+        for name in ("cfg1", "cfg2_rules", "cfg3"):
             a2 = copy.copy(args)
             a2.config = name
             t0 = time.time()
