@@ -224,7 +224,8 @@ int links_simulate_noalloc(links_ctx* ctx, const links_batch* batch, const links
  * the call is asynchronous on `stream`.  Pieces are device data and are not
  * checked on the host: each must describe a block inside buf; a row whose piece
  * has J outside [1, out->J] or a candidate index outside [0, size) is left
- * empty (n = 0).  Errors: LINKS_ERR_ARG for NULL arrays, count outside
+ * empty (n = 0), and so is a candidate with more joints than its request's
+ * stride (links_simulate at that stride reports it BAD_MECH, as it does n = 0).  Errors: LINKS_ERR_ARG for NULL arrays, count outside
  * [0, out->B], npieces < 1 with count > 0, or out->J outside [1, 32]. */
 typedef struct {
   int64_t src;   /* byte offset of the request's block in buf */

@@ -62,7 +62,10 @@ __global__ void __launch_bounds__(kGatherBlock) gather_kernel(const uint8_t* buf
   const BlockParts bp = parts_of(pc.size, Jr);
   const uint8_t* blk = buf + pc.src;
   if (j == 0) {
-    n[k] = blk[bp.n + i];
+    // more joints than the request's stride: malformed at that stride (BAD_MECH
+    // there), so no joints here either
+    const uint8_t nk = blk[bp.n + i];
+    n[k] = nk > Jr ? 0 : nk;
     fixed[k] = reinterpret_cast<const uint32_t*>(blk + bp.fixed)[i];
     motor[2 * k] = blk[bp.motor + 2 * i];
     motor[2 * k + 1] = blk[bp.motor + 2 * i + 1];

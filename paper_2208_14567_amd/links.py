@@ -357,12 +357,13 @@ class Context:
 
     def graph(self, b: DeviceBatch, T: int = 200, precision: int = FP32_RECHECK, write: int = WRITE_NONE,
               out_joint: int = -1, path_dtype: int = F32, cap: Optional[int] = None, eps_disc: float = 1e-6,
-              eps_branch: float = 1e-5, tau_drift: float = 1e-4, out: Optional[dict] = None) -> "Graph":
+              eps_branch: float = 1e-5, tau_drift: float = 1e-4, out: Optional[dict] = None,
+              T_prefilter: int = 0, branch: int = BRANCH_CONTINUITY) -> "Graph":
         """Records the launch sequence of ``simulate`` with these arguments into a HIP
         graph; ``Graph.launch`` replays it on the current stream.  The returned
         graph holds the batch and output tensors (``Graph.out``)."""
         cb, opts, so, res = self._sim_args(b, T, precision, write, out_joint, path_dtype, cap, eps_disc, eps_branch,
-                                           tau_drift, out)
+                                           tau_drift, out, T_prefilter, branch)
         g = P()
         _check(load().links_graph_create(self._h, ctypes.byref(cb), ctypes.byref(opts), ctypes.byref(so),
                                          ctypes.byref(g)), "links_graph_create")

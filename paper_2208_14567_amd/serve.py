@@ -307,19 +307,21 @@ class Server:
     capacity    bytes of the device ring that holds admitted requests
     tick_max    most candidates one tick simulates
     J           the widest joint stride a request may have
+    precision   links.FP32_RECHECK, FP64 or FP32_ONLY for every tick
+    branch      links.BRANCH_CONTINUITY or BRANCH_ORIENTATION for every tick
     min_class   smallest tick size class (a graph per class and lane)
     max_pieces  most requests one tick takes candidates from
     """
 
     def __init__(self, capacity: int = 1 << 30, tick_max: int = 1 << 19, J: int = 20, T: int = 200,
                  precision: int = 0, device: int = 0, lanes: int = 2, min_class: int = 4096,
-                 max_pieces: int = 8192):
+                 max_pieces: int = 8192, branch: int = 0):
         import torch
         from . import links
         if not 1 <= J <= 32:
             raise ValueError("J must be in 1..32")
         self.L = links
-        self.T, self.J, self.precision = T, J, precision
+        self.T, self.J, self.precision, self.branch = T, J, precision, branch
         self.tick_max = tick_max
         self.capacity = _align(capacity)
         self.classes = size_classes(tick_max, min_class)
@@ -354,7 +356,7 @@ class Server:
                 out = {"status": lane.status[:c], "fail_step": lane.fail_step[:c], "esc_step": lane.esc_step[:c],
                        "path": lane.path[:c], "path_index": lane.path_index[:c], "n_written": lane.n_written}
                 lane.graphs[c] = lane.ctx.graph(lane.prefix(L, c), T=self.T, precision=self.precision,
-                                                write=L.WRITE_VALID, cap=c, out=out)
+                                                write=L.WRITE_VALID, cap=c, out=out, branch=self.branch)
             lane.batch.n.zero_()
             torch.cuda.synchronize()
             for c in self.classes:

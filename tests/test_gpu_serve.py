@@ -37,8 +37,8 @@ def _narrow(host, Jr):
     return gen.Batch(b.n, np.ascontiguousarray(b.adj[:, :Jr]), b.fixed, b.motor, np.ascontiguousarray(b.x0[:, :Jr]))
 
 
-def _alone(L, ctx, b, T):
-    r = ctx.simulate(b, T=T, write=L.WRITE_VALID, cap=b.B)
+def _alone(L, ctx, b, T, **kw):
+    r = ctx.simulate(b, T=T, write=L.WRITE_VALID, cap=b.B, **kw)
     k = int(r["n_written"].cpu()[0])
     return {"status": r["status"].cpu().numpy(), "fail_step": r["fail_step"].cpu().numpy(),
             "esc_step": r["esc_step"].cpu().numpy(), "idx": r["path_index"][:k].cpu().numpy().astype(np.int64),
@@ -70,6 +70,9 @@ def test_gather_bytes(L):
     buf = torch.full((total,), 0xAB, dtype=torch.uint8, device="cuda")
     for b, s in zip(reqs, starts):
         serve._write_block(buf, s, b, serve.block_layout(b.B, b.J)[0])
+    # candidate 5 of the stride-8 request claims 11 joints: malformed at its stride
+    off1 = serve.block_layout(reqs[1].B, reqs[1].J)[0]
+    buf[starts[1] + off1["n"] + 5] = 11
     # pieces: a tail, a whole request, a one-candidate request, a head, and one bad piece (J > out J)
     J, rows = 20, 1400
     plan = [(0, 650, 50), (1, 0, 333), (2, 0, 1), (3, 0, 60), (0, 0, 10)]
@@ -95,7 +98,10 @@ def test_gather_bytes(L):
             assert out.n[sl].eq(0).all()          # the malformed piece's rows are left empty
         else:
             Jr = b.J
-            assert torch.equal(out.n[sl], b.n[first:first + take])
+            want = b.n[first:first + take].clone()
+            if ri == 1:
+                want[5 - first] = 0                # more joints than its stride: no joints
+            assert torch.equal(out.n[sl], want)
             assert torch.equal(out.fixed[sl], b.fixed[first:first + take])
             assert torch.equal(out.motor[sl], b.motor[first:first + take])
             assert torch.equal(out.adj[sl, :Jr], b.adj[first:first + take])
@@ -173,3 +179,28 @@ def test_poisson_stream_small(L):
     for j in (0, 17, 59):
         _check(reqs[j], _alone(L, ctx, pool.slice(int(offs[j]), int(offs[j] + sizes[j])), 200))
     srv.close()
+
+
+def test_fp64_and_orientation_ticks(L):
+    """Ticks replayed in plain FP64 with the starting-orientation rule equal solo
+    calls with the same options."""
+    from paper_2208_14567_amd import serve
+    T = 120
+    host = gen.workload("dyad_4_20", 30000, seed=9)
+    pool = L.to_device(host)
+    narrow = L.to_device(_narrow(host, 7))
+    ctx = L.Context(0)
+    kw = dict(precision=L.FP64, branch=L.BRANCH_ORIENTATION)
+    batches = [pool.slice(0, 4000), narrow.slice(0, 1500), pool.slice(4000, 4001), pool.slice(5000, 11000),
+               narrow.slice(1500, 1600)]
+    refs = [_alone(L, ctx, b, T, **kw) for b in batches]
+    srv = serve.Server(capacity=4 << 20, tick_max=3000, J=20, T=T, min_class=256, **kw)
+    srv.warm()
+    reqs = [srv.submit(b) for b in batches]
+    srv.drain()
+    torch.cuda.synchronize()
+    assert srv.ticks >= 4
+    for r, ref in zip(reqs, refs):
+        _check(r, ref)
+    srv.close()
+    _say(f"[serve] FP64, orientation rule: {srv.ticks} ticks equal to the solo calls")
