@@ -75,6 +75,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def emit(rec: dict, args):
+    """Prints the record as one JSON line; with --log also appends it to a JSONL
+    file together with the time, the device and the host."""
+    print(json.dumps(rec), flush=True)
+    if args.log:
+        import torch
+        entry = {"time": time.time(), "argv": sys.argv[1:], "config": args.config,
+                 "device": torch.cuda.get_device_name(0) if torch.cuda.is_available() else None,
+                 "host": {"cpu": cpu_model(), "nproc": os.cpu_count()}, "record": rec}
+        with open(args.log, "a") as f:
+            f.write(json.dumps(entry) + "\n")
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -100,19 +113,21 @@ def serve_leg(L, gen, dev, n_req, cfg=None):
     device memory); each tick is one gather and one graph replay."""
     import torch
     from paper_2208_14567_amd import serve
+    from paper_2208_14567_amd.configs import CONFIGS
+    c4 = CONFIGS["cfg4"]
     t0 = time.time()
-    pool_B = 500_000
-    pool = L.to_device(gen.workload("dyad_4_20", pool_B, seed=4), dev)
-    sizes = serve.request_sizes(n_req, seed=4)
-    offs = np.random.default_rng(44).integers(0, pool_B - sizes + 1)
+    pool_B = c4["pool"]
+    pool = L.to_device(gen.workload(c4["workload"], pool_B, seed=c4["seed"]), dev)
+    sizes = serve.request_sizes(n_req, seed=c4["seed"], lo=c4["sizes"][0], hi=c4["sizes"][1])
+    offs = np.random.default_rng(c4["offsets_seed"]).integers(0, pool_B - sizes + 1)
     total = int(sizes.sum())
     requests = [serve.pack(pool.slice(int(o), int(o + s))) for o, s in zip(offs, sizes)]
     torch.cuda.synchronize()
     log(f"serving pool of {pool_B} candidates and {n_req} packed requests in {time.time() - t0:.1f}s")
-    tick_max = 1 << 20
+    tick_max = c4["tick_max"]
 
     def run(arrivals):
-        srv = serve.Server(capacity=2 << 30, tick_max=tick_max, J=20, T=200)
+        srv = serve.Server(capacity=c4["ring_bytes"], tick_max=tick_max, J=20, T=c4["T"])
         tc = time.perf_counter()
         srv.warm(cfg)       # graphs of every tick size class, outside the measurement
         capture_s = time.perf_counter() - tc
@@ -129,9 +144,9 @@ def serve_leg(L, gen, dev, n_req, cfg=None):
     out = {"workload": "requests of 1..200k candidates (log-uniform), n~U{4..20}, T=200, FP32 with FP64 escalation",
            "requests": n_req, "candidates": total, "saturated": sat}
     log(f"serving saturated: {sat}")
-    for rho in (0.5, 0.8):
+    for rho in c4["loads"]:
         rate = rho * sat["sims_per_s"] / sizes.mean()
-        st = run(serve.poisson_arrivals(n_req, rate, seed=4))
+        st = run(serve.poisson_arrivals(n_req, rate, seed=c4["seed"]))
         st["arrival_rate_per_s"] = rate
         out[f"rho_{rho}"] = st
         log(f"serving rho={rho}: {st}")
@@ -195,9 +210,11 @@ def stream_config(args, L, gen, oracle, tune, dev, threads):
     simulation)."""
     import torch
     from paper_2208_14567_amd import stream as S
-    CH, T, seed = 4_000_000, args.T, 5
+    from paper_2208_14567_amd.configs import CONFIGS
+    c5 = CONFIGS["cfg5"]
+    CH, T, seed = c5["chunk"], args.T, c5["seed"]
     nch = args.chunks
-    cap = 1_000_000
+    cap = c5["cap"]
     cfg = S.StreamConfig(seed=seed, chunks=nch, chunk=CH, T=T, cap=cap)
     # tune once on a generated chunk, then use the setting on both lanes
     tctx = L.Context(0)
@@ -314,11 +331,12 @@ def other_config(args, L, gen):
     import torch
     import oracle
     from paper_2208_14567_amd import tune
+    from paper_2208_14567_amd.configs import CONFIGS
     dev = torch.device("cuda:0")
     T = args.T
     threads = min(os.cpu_count() or 1, 64)
     if args.config == "cfg1":
-        host = gen.workload("fourbar", 10_000, seed=1)
+        host = gen.workload(CONFIGS["cfg1"]["workload"], CONFIGS["cfg1"]["candidates"], seed=CONFIGS["cfg1"]["seed"])
         db = L.to_device(host, dev)
         ctx = L.Context(0)
         t0 = time.perf_counter()
@@ -374,10 +392,11 @@ def other_config(args, L, gen):
     if args.config == "cfg2_rules":
         # the headline's shape with the paper's topology rules ("Generating Valid
         # Topologies"): the same step, valid paths written, far fewer survivors
-        B = 1_000_000
+        cr = CONFIGS["cfg2_rules"]
+        B = cr["candidates"]
         ctx = L.Context(0)
         # generated on the device (the host generator's candidates, bit for bit)
-        db = ctx.generate_dyads(B, 11, J=20, n_lo=6, n_hi=20, rules=True)
+        db = ctx.generate_dyads(B, cr["seed"], J=20, n_lo=6, n_hi=20, rules=True)
         tuned = tune.autotune(ctx, db, T=T, precision=L.FP32_RECHECK, use_cache=False, write=L.WRITE_VALID, cap=B)
         dt, passes, r = time_sim(ctx, db, reps=10, T=T, precision=L.FP32_RECHECK, write=L.WRITE_VALID, cap=B)
         st = r["status"].cpu().numpy()
@@ -385,7 +404,7 @@ def other_config(args, L, gen):
         ctx64 = L.Context(0)
         dt64, passes64, _ = time_sim(ctx64, db, reps=10, T=T, precision=L.FP64, write=L.WRITE_VALID, cap=B)
         k = 20_000
-        sample = gen.dyad_batch(k, 11, gen.n_uniform(6, 20), 20, rules=True)  # the first k, on the host
+        sample = gen.dyad_batch(k, cr["seed"], gen.n_uniform(6, 20), 20, rules=True)  # the first k, on the host
         t1 = time.perf_counter()
         ref = oracle.simulate(sample, T=T, margins=True, nthreads=threads)
         t_or = time.perf_counter() - t1
@@ -407,8 +426,9 @@ def other_config(args, L, gen):
                                                    "in_band_equal": float(agree[~clear].mean()) if (~clear).any()
                                                    else None}}}
     # cfg3: 4M skewed joint counts, autotuned
-    B = 4_000_000
-    host = gen.workload("dyad_skewed", B, seed=3)
+    c3 = CONFIGS["cfg3"]
+    B = c3["candidates"]
+    host = gen.workload(c3["workload"], B, seed=c3["seed"])
     db = L.to_device(host, dev)
     ctx = L.Context(0)
     tuned = tune.autotune(ctx, db, T=T, precision=L.FP32_RECHECK, use_cache=False)
@@ -564,8 +584,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--B", type=int, default=1_000_000)
-    ap.add_argument("--T", type=int, default=200)
+    from paper_2208_14567_amd.configs import CONFIGS as _C
+    ap.add_argument("--B", type=int, default=_C["cfg2"]["candidates"])
+    ap.add_argument("--T", type=int, default=_C["cfg2"]["T"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 leg")
     ap.add_argument("--handover", choices=["exact", "fast"], default="fast",
@@ -576,8 +597,8 @@ def main():
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the secondary configurations (10k four-bars, 1M with the topology rules, "
                          "4M skewed joint counts)")
-    ap.add_argument("--serve-requests", type=int, default=2000)
-    ap.add_argument("--chunks", type=int, default=25, help="cfg5: chunks of 4M candidates")
+    ap.add_argument("--serve-requests", type=int, default=_C["cfg4"]["requests"])
+    ap.add_argument("--chunks", type=int, default=_C["cfg5"]["chunks"], help="cfg5: chunks of 4M candidates")
     ap.add_argument("--bank", type=int, default=10_000_000, help="retrieval: bank paths")
     ap.add_argument("--config", choices=["cfg2", "cfg1", "cfg1x", "cfg2_rules", "cfg3", "cfg5", "next", "retrieval"],
                     default="cfg2",
@@ -589,6 +610,8 @@ def main():
                          "and copied to the host; next: samples per valid mechanism against the joint "
                          "count and the low-fidelity screen; retrieval: chamfer search over a bank of "
                          "normalised coupler paths")
+    ap.add_argument("--log", default=None,
+                    help="also append the JSON record, with the time, device and host, to this JSONL file")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device (HBM traffic scale for counters)")
     args = ap.parse_args()
@@ -598,20 +621,22 @@ def main():
 
     import torch
     from paper_2208_14567_amd import gen, links as L
+    from paper_2208_14567_amd.configs import CONFIGS
 
     if args.config == "next":
-        print(json.dumps(next_config(args, L, gen)))
+        emit(next_config(args, L, gen), args)
         return
     if args.config == "retrieval":
-        print(json.dumps(retrieval_config(args, L, gen)))
+        emit(retrieval_config(args, L, gen), args)
         return
     if args.config != "cfg2":
-        print(json.dumps(other_config(args, L, gen)))
+        emit(other_config(args, L, gen), args)
         return
     dev = torch.device("cuda:0")
+    c2 = CONFIGS["cfg2"]
     B, T = args.B, args.T
     t0 = time.time()
-    host = gen.workload("dyad_6_20", B, seed=2)
+    host = gen.workload(c2["workload"], B, seed=c2["seed"])
     log(f"generated {B} candidates in {time.time() - t0:.1f}s")
     db = L.to_device(host, dev)
     ctx = L.Context(0)
@@ -837,7 +862,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         res["copy_probe_bytes"] = nb
-    print(json.dumps(res))
+    emit(res, args)
 
 
 if __name__ == "__main__":
