@@ -222,11 +222,13 @@ class Streamer:
             max_chunks: Optional[int] = None, inspect: Optional[Callable] = None) -> dict:
         """Runs the stream from its resume point (chunk 0 without a progress file)
         to the end, or for at most max_chunks chunks; returns the totals of the
-        chunks delivered so far, the next chunk and the wall time of this run."""
+        chunks delivered so far (those the progress file records included), the
+        next chunk and the wall time of this run."""
         import torch
         cfg = self.cfg
         progress = Progress(progress_path) if progress_path else None
         start = 0
+        self.totals = {"candidates": 0, "valid": 0, "dropped": 0, "d2h_bytes": 0}
         if progress is not None:
             st = progress.load(cfg)
             if st is not None:
