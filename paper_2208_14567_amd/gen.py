@@ -172,7 +172,24 @@ def dyad_batch(B: int, seed: int, n_dist: Callable[[np.ndarray], np.ndarray], J:
     out = empty_batch(B, J)
     for lo in range(0, B, chunk):
         hi = min(B, lo + chunk)
-        _dyad_chunk(out, lo, hi, seed, n_dist, J, paper_mode, first, rules)
+        cand = np.arange(first + lo, first + hi, dtype=np.uint64)
+        _dyad_chunk(out, lo, hi, seed, n_dist, J, paper_mode, cand, rules)
+    return out
+
+
+def dyad_batch_at(index, seed: int, n_dist: Callable[[np.ndarray], np.ndarray], J: int = 20,
+                  paper_mode: bool = False, rules: bool = False, chunk: int = 1 << 20) -> Batch:
+    """The candidates of ``dyad_batch`` at the given indices of the seed's sequence
+    (any order, repeats allowed): row i equals row index[i] - first of a
+    ``dyad_batch`` that covers it, since every draw depends only on (seed,
+    candidate index, draw number)."""
+    idx = np.asarray(index, dtype=np.int64).reshape(-1)
+    if idx.size and idx.min() < 0:
+        raise ValueError("candidate indices must be non-negative")
+    out = empty_batch(idx.size, J)
+    for lo in range(0, idx.size, chunk):
+        hi = min(idx.size, lo + chunk)
+        _dyad_chunk(out, lo, hi, seed, n_dist, J, paper_mode, idx[lo:hi].astype(np.uint64), rules)
     return out
 
 
@@ -204,10 +221,10 @@ def _rules_feasible(U: np.ndarray, fixed: np.ndarray, r: np.ndarray) -> np.ndarr
     return (_popcount(U) <= r + 1) & (_popcount(U & fixed) <= r - 1)
 
 
-def _dyad_chunk(out: Batch, lo: int, hi: int, seed: int, n_dist, J: int, paper_mode: bool, first: int,
+def _dyad_chunk(out: Batch, lo: int, hi: int, seed: int, n_dist, J: int, paper_mode: bool, cand: np.ndarray,
                 rules: bool = False):
+    """Rows lo..hi of out: the candidates with the global indices cand."""
     m = hi - lo
-    cand = np.arange(first + lo, first + hi, dtype=np.uint64)
     st = stream_state(seed, cand)
     n = n_dist(draw_u24(st, DRAW_N)).astype(np.int64)
     if n.min() < 3 or n.max() > J:

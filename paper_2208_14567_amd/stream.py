@@ -147,16 +147,21 @@ class Streamer:
     call only.  A chunk with more valid candidates than cfg.cap delivers the first
     cap of them and counts the rest as dropped.  With keep_status = m > 0,
     inspect(c, status, fail_step) also receives the statuses and failure steps of
-    the chunk's first m candidates (views, valid during the call).
+    the chunk's candidates 0, s, 2s, ... (s = status_stride), the first m of them
+    (views, valid during the call).
     """
 
-    def __init__(self, cfg: StreamConfig, device: int = 0, tuning: Optional[dict] = None, keep_status: int = 0):
+    def __init__(self, cfg: StreamConfig, device: int = 0, tuning: Optional[dict] = None, keep_status: int = 0,
+                 status_stride: int = 1):
         from . import links
         if cfg.chunk <= 0 or cfg.chunks < 0 or cfg.cap <= 0:
             raise ValueError("chunk and cap must be positive, chunks non-negative")
         self.L = links
         self.cfg = cfg
-        self.keep = max(0, min(keep_status, cfg.chunk))
+        if status_stride < 1:
+            raise ValueError("status_stride must be positive")
+        self.stride = status_stride
+        self.keep = max(0, min(keep_status, -(-cfg.chunk // status_stride)))
         self.lanes = [_Lane(links, device, cfg, self.keep) for _ in range(2)]
         if tuning:
             from . import tune
@@ -193,8 +198,9 @@ class Streamer:
             lane.h_index[:kk].copy_(lane.out["path_index"][:kk], non_blocking=True)
             lane.h_xform[:kk].copy_(lane.xform[:kk], non_blocking=True)
             if self.keep:
-                lane.h_status.copy_(lane.out["status"][:self.keep], non_blocking=True)
-                lane.h_fail.copy_(lane.out["fail_step"][:self.keep], non_blocking=True)
+                sel = slice(0, self.keep * self.stride, self.stride)
+                lane.h_status.copy_(lane.out["status"][sel], non_blocking=True)
+                lane.h_fail.copy_(lane.out["fail_step"][sel], non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(lane.stream)
         rec = _Copied(lane.chunk, k, ev, lane)

@@ -21,6 +21,21 @@ def test_counter_based_and_fp32_exact():
     assert np.all((x * 2 ** 24) == np.floor(x * 2 ** 24)) and x.min() >= 0 and x.max() < 1
 
 
+@pytest.mark.parametrize("paper,rules", [(False, False), (True, False), (False, True)])
+def test_candidates_at_indices_equal_the_batch_rows(paper, rules):
+    nd = gen.n_uniform(6, 20)
+    b = gen.dyad_batch(3000, 7, nd, 20, paper_mode=paper, first=5000, rules=rules)
+    idx = np.random.default_rng(3).integers(5000, 8000, size=500)
+    idx[:3] = (7999, 5000, 7999)  # both ends, a repeat
+    a = gen.dyad_batch_at(idx, 7, nd, 20, paper_mode=paper, rules=rules, chunk=128)
+    r = idx - 5000
+    for f in ("n", "adj", "fixed", "motor", "x0"):
+        assert np.array_equal(getattr(a, f), getattr(b, f)[r]), f
+    assert gen.dyad_batch_at([], 7, nd).B == 0
+    with pytest.raises(ValueError):
+        gen.dyad_batch_at([-1], 7, nd)
+
+
 def _mobility(b):
     """Mobility m = 3(N-1) - 2 j1 of the paper's Eq. 1 with every edge a binary link
     plus one ground body; a joint joining k bodies contributes k-1 pin pairs."""

@@ -101,3 +101,25 @@ def test_stream_cap_drops_the_rest(L):
     tot = S.Streamer(cfg).run(sink=c)
     assert all(len(v[0]) == 100 for v in c.got.values())
     assert tot["dropped"] == tot["valid"] - 200 > 0
+
+
+def test_stream_inspect_strided_statuses(L):
+    from paper_2208_14567_amd import stream as S
+    cfg = S.StreamConfig(seed=24, chunks=3, chunk=20000, cap=20000)
+    seen = {}
+
+    def inspect(c, status, fail_step):
+        seen[c] = (status.copy(), fail_step.copy())
+
+    # 20000 / 7 rounds up to 2858 candidates per chunk; the keep is capped there
+    S.Streamer(cfg, keep_status=5000, status_stride=7).run(inspect=inspect)
+    assert sorted(seen) == [0, 1, 2]
+    ctx = L.Context(0)
+    db = ctx.generate_dyads(cfg.chunk, cfg.seed, first=2 * cfg.chunk)
+    r = ctx.simulate(db, T=cfg.T, write=L.WRITE_VALID, cap=cfg.cap)
+    st, fs = seen[2]
+    assert len(st) == 2858
+    assert np.array_equal(st, r["status"].cpu().numpy()[::7])
+    assert np.array_equal(fs, r["fail_step"].cpu().numpy()[::7])
+    with pytest.raises(ValueError):
+        S.Streamer(cfg, keep_status=10, status_stride=0)
