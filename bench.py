@@ -406,6 +406,8 @@ def other_config(args, L, gen):
         st = r["status"].cpu().numpy()
         fs = r["fail_step"].cpu().numpy()
         ctx64 = L.Context(0)
+        tuned64 = tune.autotune(ctx64, db, T=T, precision=L.FP64, use_cache=False, write=L.WRITE_VALID, cap=B,
+                                space={"chunk": tune.SPACE["chunk"], "refill64": [1, 8, 32], "wave64": [0, 2, 6]})
         dt64, passes64, _ = time_sim(ctx64, db, reps=10, T=T, precision=L.FP64, write=L.WRITE_VALID, cap=B)
         k = 20_000
         sample = gen.dyad_batch(k, cr["seed"], gen.n_uniform(6, 20), 20, rules=True)  # the first k, on the host
@@ -420,7 +422,8 @@ def other_config(args, L, gen):
                                        "depends on every joint and is linked to no fixed joint), n~U{6..20}, "
                                        "x0~U[0,1)^2, T=200, FP32 with FP64 escalation, valid paths written",
                            "candidates": B, "T": T, "seed": 11},
-                "fp64_plain": {"value": B / dt64, "ms_per_step": dt64 * 1e3, "passes_ms": passes64},
+                "fp64_plain": {"value": B / dt64, "ms_per_step": dt64 * 1e3, "passes_ms": passes64,
+                               "tuning": tuned64["config"]},
                 "valid_fraction": float((st == 0).mean()),
                 "escalated_fraction": float((r["esc_step"].cpu().numpy() >= 0).mean()),
                 "cpu_baseline": {"value": k / t_or, "unit": "sims/s", "cores": threads, "kind": "oracle",
@@ -440,7 +443,7 @@ def other_config(args, L, gen):
     st = r["status"].cpu().numpy()
     ctx64 = L.Context(0)
     tuned64 = tune.autotune(ctx64, db, T=T, precision=L.FP64, use_cache=False,
-                            space={"chunk": tune.SPACE["chunk"], "refill64": [1, 8, 32]})
+                            space={"chunk": tune.SPACE["chunk"], "refill64": [1, 8, 32], "wave64": [0, 2, 6]})
     dt64, passes64, r64 = time_sim(ctx64, db, reps=10, T=T, precision=L.FP64)
     # CPU baseline: the oracle on a random sample, with the GPU's agreement on it
     idx = np.random.default_rng(0).choice(B, 20000, replace=False)
@@ -715,7 +718,7 @@ def main():
         tuned64 = None
         if not args.no_tune:
             tuned64 = tune.autotune(ctx64, db, T=T, precision=L.FP64, use_cache=False, write=L.WRITE_VALID, cap=B,
-                                    space={"chunk": tune.SPACE["chunk"], "refill64": [1, 8, 32]})
+                                    space={"chunk": tune.SPACE["chunk"], "refill64": [1, 8, 32], "wave64": [0, 2, 6]})
             log(f"autotune fp64: {tuned64['config']} ({tuned64['ms']:.3f} ms)")
         sec64, pass64 = run(ctx64, L.FP64, "fp64 plain")
         st64 = out["status"].cpu().numpy()

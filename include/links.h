@@ -277,12 +277,18 @@ int links_set_tuning(links_ctx* ctx, int waves32, int refill_min, int waves64);
  *                     the default: never; 65: every wave at once);
  *   "sort_esc"        1: the FP64 hand-over pass takes its queue ordered by
  *                     hand-over step, earliest first; 0 (default): as handed over;
+ *   "wave64"          FP64 passes with one candidate per wave, its joint
+ *                     positions in registers and 63 steps decided per round (up to
+ *                     20 joints; not with "deesc" > 0), a bit mask: 1 the hand-over
+ *                     pass, 2 the path pass (rows whole), 4 the FP64 decision pass
+ *                     of LINKS_FP64; 0 (default): none.  Results are the same
+ *                     either way;
  *   "path_chunks"     1 (default): path rows are computed in chunks of 32 steps,
  *                     each on a lane of its own, from the sides of every placed
  *                     joint that the decision passes record at the chunk ends
  *                     (FP64 and FP32_RECHECK precision; not with "par32",
- *                     "drain32", "deesc" > 0 or "par64" = 2); 0: whole rows.  Rows
- *                     are the same either way. */
+ *                     "drain32", "deesc" > 0, "par64" = 2 or the path pass of
+ *                     "wave64"); 0: whole rows.  Rows are the same either way. */
 int links_set_option(links_ctx* ctx, const char* name, int value);
 /* Current value of a named option in *value (LINKS_ERR_ARG for an unknown name). */
 int links_get_option(links_ctx* ctx, const char* name, int* value);

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblinks.so")
-SOURCES = ["api.cpp", "prep.hip", "sim32.hip", "sim64.hip", "normalize.hip", "gen.hip", "chamfer.hip", "noalloc.hip", "serve.hip"]
+SOURCES = ["api.cpp", "prep.hip", "sim32.hip", "sim64.hip", "normalize.hip", "gen.hip", "chamfer.hip", "noalloc.hip", "serve.hip", "simwave.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("LINKS_OFFLOAD_ARCH", "gfx950")
 

@@ -96,6 +96,10 @@ struct links_ctx {
   // path rows computed in chunks of kPathChunk steps from the sides the decision
   // passes record (else whole, step by step)
   bool path_chunks = true;
+  // FP64 passes with one candidate per wave and its positions in registers
+  // (up to 20 joints): bit 0 the hand-over pass, bit 1 the path pass (whole rows),
+  // bit 2 the FP64 decision pass of FP64 precision
+  int wave64 = 0;
   std::map<std::string, int> occ_cache;
   // last call's statistics
   int last_grid32 = 0, last_grid64 = 0;
@@ -422,6 +426,11 @@ int links_set_option(links_ctx* ctx, const char* name, int value) {
     ctx->par64 = value;
     return LINKS_OK;
   }
+  if (k == "wave64") {
+    if (value < 0 || value > 7) return fail(LINKS_ERR_ARG, "wave64 must be in 0..7");
+    ctx->wave64 = value;
+    return LINKS_OK;
+  }
   return fail(LINKS_ERR_ARG, "unknown option '%s'", name);
 }
 
@@ -442,6 +451,7 @@ int links_get_option(links_ctx* ctx, const char* name, int* value) {
   else if (k == "drain32") *value = ctx->drain32;
   else if (k == "sort_esc") *value = ctx->sort_esc ? 1 : 0;
   else if (k == "path_chunks") *value = ctx->path_chunks ? 1 : 0;
+  else if (k == "wave64") *value = ctx->wave64;
   else return fail(LINKS_ERR_ARG, "unknown option '%s'", name);
   return LINKS_OK;
 }
@@ -592,7 +602,13 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   // (FP32_ONLY), whose FP32 sides near a tie need not be those the FP64 path
   // pass takes.
   const int ck_n = (T + kPathChunk - 1) / kPathChunk;
-  const bool chunks = ctx->path_chunks && opts->write != LINKS_WRITE_NONE &&
+  // the FP64 passes a wave-per-candidate kernel runs (up to 20 joints; not with the
+  // return to FP32 after a hand-over)
+  const bool wave_ok = sim64_wave_fits(J) && ctx->deesc == 0;
+  const bool wave_esc = wave_ok && (ctx->wave64 & 1) && ctx->par64 >= 1;
+  const bool wave_path = wave_ok && (ctx->wave64 & 2);
+  const bool wave_perm = wave_ok && (ctx->wave64 & 4);
+  const bool chunks = !wave_path && ctx->path_chunks && opts->write != LINKS_WRITE_NONE &&
                       !(opts->write == LINKS_WRITE_VALID && out->cap == 0) && ck_n > 1 && ctx->par64 != 2 &&
                       (opts->precision == LINKS_FP64 ||
                        (opts->precision == LINKS_FP32_RECHECK && !ctx->par32 && ctx->deesc == 0 && ctx->drain32 == 0));
@@ -748,7 +764,11 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   SimArgs sa64 = sa;
   sa64.refill_min = ctx->refill64;
   // an FP64 pass, step by step or parallel in time
-  auto run64 = [&](const SimArgs& a, int source, bool exact, LaunchCfg cfg, bool par) -> hipError_t {
+  auto run64 = [&](const SimArgs& a, int source, bool exact, LaunchCfg cfg, bool par, bool wave = false) -> hipError_t {
+    if (wave) {
+      cfg.grid = grid_for(ctx, "wave64", sim64_wave_blocks_per_cu(J, source, exact, cfg.waves));
+      return launch_sim64_wave(a, source, exact, cfg, st);
+    }
     if (par) {
       cfg.seg = source == kFromEsc ? ctx->seg64 : 16;
       cfg.grid = grid_for(ctx, "par64", sim64_par_blocks_per_cu(J, source, exact, cfg.waves, cfg.seg));
@@ -760,7 +780,7 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   if (fp64) {
     c64.grid = grid_for(ctx, "sim64", sim64_blocks_per_cu(J, kFromPerm, true, c64.waves, lds64));
     if ((rc = mark(ctx, 3, st))) return rc;
-    HIP_CHECK(run64(sa64, kFromPerm, true, c64, ctx->par64 == 2));
+    HIP_CHECK(run64(sa64, kFromPerm, true, c64, ctx->par64 == 2, wave_perm));
     mark_used(ctx, 3);
     ctx->last_grid32 = 0;
   } else {
@@ -807,7 +827,7 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
       h1.esc = esc_sorted;
     }
     const bool par_h = ctx->par64 >= 1 && ctx->deesc == 0;
-    HIP_CHECK(run64(h1, kFromEsc, ctx->exact_handover, c64, par_h));
+    HIP_CHECK(run64(h1, kFromEsc, ctx->exact_handover, c64, par_h, wave_esc));
     if (ctx->deesc > 0) {
       // the returned candidates continue in FP32 (their own counters and
       // hand-over queue), and what they hand over again is finished in FP64
@@ -845,7 +865,7 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   // written straight into its output row
   if ((rc = mark(ctx, 5, st))) return rc;
   if (opts->write != LINKS_WRITE_NONE && !(opts->write == LINKS_WRITE_VALID && out->cap == 0)) {
-    HIP_CHECK(run64(sa64, kFromPath, fp64, c64, ctx->par64 == 2));
+    HIP_CHECK(run64(sa64, kFromPath, fp64, c64, ctx->par64 == 2, wave_path));
     mark_used(ctx, 5);
   }
   if ((rc = mark(ctx, 6, st))) return rc;

@@ -156,6 +156,11 @@ int sim64_blocks_per_cu(int J, int source, bool exact, int waves, int lds_bytes)
 // the same passes computed parallel in time (16-lane segments per candidate)
 hipError_t launch_sim64_par(const SimArgs& a, int source, bool exact, const LaunchCfg& cfg, hipStream_t st);
 int sim64_par_blocks_per_cu(int J, int source, bool exact, int waves, int seg);
+// the same passes with one candidate per wave and its positions in registers
+// (simwave.hip); up to 20 joints (sim64_wave_fits)
+bool sim64_wave_fits(int J);
+hipError_t launch_sim64_wave(const SimArgs& a, int source, bool exact, const LaunchCfg& cfg, hipStream_t st);
+int sim64_wave_blocks_per_cu(int J, int source, bool exact, int waves);
 
 // Path normalisation, one wave per path.
 hipError_t launch_normalize(const float* paths, int32_t P, const int32_t* count, int32_t T, int32_t mode,

@@ -12,6 +12,9 @@ workload (batch size, joint-count mix, step count) and the device:
   drain32     once the work list is exhausted, FP32 waves with fewer active lanes
               than this hand their candidates to the parallel-in-time pass (0: never)
   sort_esc    the FP64 hand-over pass takes its queue ordered by hand-over step
+  wave64      FP64 passes with one candidate per wave and its positions in
+              registers: 2 the path pass (whole rows, 63 steps per round), 6 also
+              the FP64 decision pass of FP64 precision (0: none)
 
 `autotune` runs the real pass sequence on the caller's batch, timing each
 candidate setting with the library's own HIP events, and searches coordinate by
@@ -37,10 +40,11 @@ SPACE: Dict[str, List[int]] = {
     "deesc": [0, 8],
     "drain32": [0, 16, 32],
     "sort_esc": [0, 1],
+    "wave64": [0, 2],
 }
 
 DEFAULTS: Dict[str, int] = {"waves32": 4, "refill_min": 32, "chunk": 128, "spread": 1, "refill64": 32, "deesc": 0,
-                            "drain32": 0, "sort_esc": 0}
+                            "drain32": 0, "sort_esc": 0, "wave64": 0}
 
 
 def cache_path() -> str:
@@ -84,7 +88,7 @@ def coordinate_search(measure: Callable[[Dict[str, int]], float], space: Dict[st
 def apply(ctx, cfg: Dict[str, int]):
     cur = ctx.get_tuning()
     ctx.set_tuning(cfg.get("waves32", cur["waves32"]), cfg.get("refill_min", cur["refill_min"]), cur["waves64"])
-    for k in ("chunk", "spread", "refill64", "deesc", "drain32", "sort_esc"):
+    for k in ("chunk", "spread", "refill64", "deesc", "drain32", "sort_esc", "wave64"):
         if k in cfg:
             ctx.set_option(k, cfg[k])
 

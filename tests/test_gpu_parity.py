@@ -245,6 +245,61 @@ def test_handover_queue_order(ctx, L):
         assert np.array_equal(a["path"], z["path"], equal_nan=True), key
 
 
+@pytest.mark.parametrize("name,B,seed,T,branch", [("dyad_6_20", 30000, 41, 200, 0), ("dyad_4_20", 20000, 42, 77, 0),
+                                                  ("paper_8_20", 8000, 43, 200, 0), ("dyad_skewed", 20000, 44, 1500, 0),
+                                                  ("dyad_6_20", 20000, 45, 200, 1), ("fourbar_u", 5000, 46, 200, 0)])
+def test_wave_per_candidate_fp64_passes(ctx, L, name, B, seed, T, branch):
+    """The FP64 passes with one candidate per wave (positions in registers, 63
+    steps per round) take every decision of the segmented and step-by-step passes:
+    statuses, failure and hand-over steps and path rows equal bit for bit, for the
+    hand-over pass, the path pass and the FP64 decision pass, alone and together."""
+    _say(f"[wave64] {name} B={B} T={T} branch={branch}")
+    b = gen.workload(name, B, seed=seed)
+    db = L.to_device(b)
+    prev = ctx.get_option("wave64")
+    res = {}
+    try:
+        for precision in (L.FP32_RECHECK, L.FP64):
+            for mode in (0, 1, 2, 4, 7):
+                ctx.set_option("wave64", mode)
+                res[precision, mode] = _np(ctx.simulate(db, T=T, precision=precision, branch=branch,
+                                                        write=L.WRITE_ALL, path_dtype=L.F64))
+    finally:
+        ctx.set_option("wave64", prev)
+    for precision in (L.FP32_RECHECK, L.FP64):
+        a = res[precision, 0]
+        assert (a["status"] == 0).sum() > 20
+        if precision == L.FP32_RECHECK:
+            assert (a["esc_step"] >= 0).sum() > 20
+        for mode in (1, 2, 4, 7):
+            z = res[precision, mode]
+            for k in ("status", "fail_step", "esc_step"):
+                assert np.array_equal(a[k], z[k]), (precision, mode, k)
+            assert np.array_equal(a["path"], z["path"], equal_nan=True), (precision, mode)
+    ref = oracle.simulate(b, T=T, branch=branch, path=True, nthreads=NTH)
+    z = res[L.FP64, 7]
+    assert np.array_equal(z["status"], ref["status"]) and np.array_equal(z["fail_step"], ref["fail_step"])
+    assert np.array_equal(z["path"], ref["path"], equal_nan=True)
+
+
+def test_wave_per_candidate_falls_back_above_20_joints(ctx, L):
+    """Above 20 joints the wave-per-candidate kernels do not apply and the other
+    passes run: results equal with the option on or off."""
+    b = gen.Batch.concat([gen.dyad_batch(3000, 47, gen.n_uniform(6, 24), J=24)])
+    db = L.to_device(b)
+    prev = ctx.get_option("wave64")
+    try:
+        ctx.set_option("wave64", 7)
+        z = _np(ctx.simulate(db, T=200, write=L.WRITE_ALL, path_dtype=L.F64))
+        ctx.set_option("wave64", 0)
+        a = _np(ctx.simulate(db, T=200, write=L.WRITE_ALL, path_dtype=L.F64))
+    finally:
+        ctx.set_option("wave64", prev)
+    for k in ("status", "fail_step", "esc_step"):
+        assert np.array_equal(a[k], z[k]), k
+    assert np.array_equal(a["path"], z["path"], equal_nan=True)
+
+
 @pytest.mark.parametrize("precision", [0, 2])
 def test_parallel_in_time_fp32_pass(ctx, L, precision):
     """The FP32 pass computed parallel in time takes every decision of the
