@@ -3,7 +3,7 @@
 //
 // The parallel-in-time passes of sim64.hip give one candidate to a segment of
 // lanes; each lane keeps its own column of positions in LDS, which limits them to
-// about one and a half waves per SIMD.  Here the whole wave holds one candidate:
+// one and a half to two waves per SIMD.  Here the whole wave holds one candidate:
 // lane r computes step t0 - 1 + r (lane 0, the provider, holds the starting
 // positions or recomputes the last decided step), so every slot index the solve
 // order names (Methodology, "Graphical Simulator") is the same in all lanes, and
@@ -28,10 +28,13 @@ constexpr int kWvStep = kWave - 1;
 // hand-over queue entries a wave claims with one atomic
 constexpr int kWvClaim = 4;
 
-// the positions of every slot at this lane's step
-template <int NS>
-struct RegSlots {
-  typedef uint32_t V __attribute__((ext_vector_type(NS)));
+// The positions of every slot at this lane's step.  A vector of registers is
+// allocated in sizes of 1, 2, 3, 4, 5, 8, 16 or 32 words, so more than 16 slots are
+// held as a 16-slot part and a 4-slot part (80 registers for 20 slots rather than
+// 128), the part chosen by a branch on the uniform index.
+template <int N>
+struct RegPart {
+  typedef uint32_t V __attribute__((ext_vector_type(N)));
   V xl, xh, yl, yh;
   __device__ __forceinline__ double2 get(int i) const {
     return make_double2(__hiloint2double((int)xh[i], (int)xl[i]), __hiloint2double((int)yh[i], (int)yl[i]));
@@ -41,6 +44,24 @@ struct RegSlots {
     xh[i] = (uint32_t)__double2hiint(v.x);
     yl[i] = (uint32_t)__double2loint(v.y);
     yh[i] = (uint32_t)__double2hiint(v.y);
+  }
+};
+
+template <int NS>
+struct RegSlots {
+  static constexpr int N0 = NS > 16 ? 16 : NS;
+  static constexpr int N1 = NS > 16 ? NS - 16 : 1;
+  RegPart<N0> lo;
+  RegPart<N1> hi;
+  __device__ __forceinline__ double2 get(int i) const {
+    if (NS <= 16 || i < 16) return lo.get(i);
+    return hi.get(i - 16);
+  }
+  __device__ __forceinline__ void put(int i, double2 v) {
+    if (NS <= 16 || i < 16)
+      lo.put(i, v);
+    else
+      hi.put(i - 16, v);
   }
 };
 
@@ -108,11 +129,8 @@ __device__ bool drift_wave(const SimArgs& A, int cand, int item, int D, int n, c
   return false;
 }
 
-#ifndef WPE
-#define WPE 2
-#endif
 template <int DMAX, int SRC, bool EXACT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 simwave64_kernel(SimArgs A) {
   constexpr int NS = DMAX + 2;  // slots: the placed joints, the tip and the fixed joints
   const int lane = __lane_id();
