@@ -153,14 +153,20 @@ def serve_leg(L, gen, dev, n_req, cfg=None):
     return out
 
 
-def end_to_end(L, ctx, host, dev, T):
+def end_to_end(L, ctx, host, dev, T, x0_dtype=np.float64):
     """PCIe-inclusive rate: inputs from pinned host memory, simulation, valid paths
-    and their indices back to pinned host memory (one pass, after warm-up)."""
+    and their indices back to pinned host memory (one pass, after warm-up).  With
+    x0_dtype float32 the positions cross PCIe in single precision, which the
+    library widens on the device (exact here: the generator's coordinates are
+    multiples of 2^-24 in [0, 1))."""
     import torch
     B = host.B
+    x0 = host.x0.astype(x0_dtype)
+    if not np.array_equal(x0.astype(np.float64), host.x0):
+        raise ValueError("positions not exact in the requested precision")
     pinned = {k: torch.from_numpy(np.ascontiguousarray(v)).pin_memory() for k, v in (
         ("n", host.n.astype(np.uint8)), ("adj", host.adj.view(np.int32)), ("fixed", host.fixed.view(np.int32)),
-        ("motor", host.motor.astype(np.uint8)), ("x0", host.x0.astype(np.float64)))}
+        ("motor", host.motor.astype(np.uint8)), ("x0", x0))}
     dbs = {k: torch.empty(v.shape, dtype=v.dtype, device=dev) for k, v in pinned.items()}
     db = L.DeviceBatch(dbs["n"], dbs["adj"], dbs["fixed"], dbs["motor"], dbs["x0"])
     path_h = torch.empty((B, T, 2), dtype=torch.float32).pin_memory()
@@ -815,6 +821,7 @@ def main():
         serving = serve_leg(L, gen, dev, args.serve_requests, tuned["config"] if tuned else None)
 
     e2e = end_to_end(L, ctx, host, dev, T)
+    e2e["x0_f32"] = end_to_end(L, ctx, host, dev, T, x0_dtype=np.float32)
 
     # the secondary configurations in the same record: 10k four-bars against the
     # oracle, and 4M skewed joint counts with a sampled oracle check

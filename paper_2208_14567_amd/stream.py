@@ -19,6 +19,12 @@ with exactly the candidates it would have run, and a chunk delivered again after
 a crash (between its sink call and the file update) is delivered with the same
 contents.
 
+Host source: given a batch in host memory (candidates generated elsewhere),
+the stream copies chunk c's rows from pinned memory on the lane's stream instead
+of generating them, so a chunk's inputs cross PCIe while the other lane
+simulates.  Positions can cross in single precision when that is exact (the
+library widens them on the device).
+
 This module is host scheduling only; all generation, simulation and
 normalisation run in the HIP library.
 """
@@ -99,7 +105,7 @@ class NpzSink:
 
 
 class _Lane:
-    def __init__(self, links, device, cfg: StreamConfig, keep_status: int):
+    def __init__(self, links, device, cfg: StreamConfig, keep_status: int, x0_dtype=None):
         import torch
         dev = torch.device("cuda", device)
         CH, J, T, cap = cfg.chunk, cfg.J, cfg.T, cfg.cap
@@ -109,7 +115,7 @@ class _Lane:
                                        torch.empty((CH, J), dtype=torch.int32, device=dev),
                                        torch.empty(CH, dtype=torch.int32, device=dev),
                                        torch.empty((CH, 2), dtype=torch.uint8, device=dev),
-                                       torch.empty((CH, J, 2), dtype=torch.float64, device=dev))
+                                       torch.empty((CH, J, 2), dtype=x0_dtype or torch.float64, device=dev))
         self.out = {"status": torch.empty(CH, dtype=torch.uint8, device=dev),
                     "fail_step": torch.empty(CH, dtype=torch.int16, device=dev),
                     "esc_step": torch.empty(CH, dtype=torch.int16, device=dev),
@@ -152,7 +158,12 @@ class Streamer:
     """
 
     def __init__(self, cfg: StreamConfig, device: int = 0, tuning: Optional[dict] = None, keep_status: int = 0,
-                 status_stride: int = 1):
+                 status_stride: int = 1, host=None, x0_f32: bool = False):
+        """host: a batch in host memory (numpy fields n, adj, fixed, motor, x0 as
+        gen.Batch) whose row i is the stream's candidate i, at least chunks x chunk
+        rows; None: candidates generated on the device.  x0_f32: host positions
+        cross PCIe in single precision (they must be exact in it)."""
+        import torch
         from . import links
         if cfg.chunk <= 0 or cfg.chunks < 0 or cfg.cap <= 0:
             raise ValueError("chunk and cap must be positive, chunks non-negative")
@@ -162,12 +173,28 @@ class Streamer:
             raise ValueError("status_stride must be positive")
         self.stride = status_stride
         self.keep = max(0, min(keep_status, -(-cfg.chunk // status_stride)))
-        self.lanes = [_Lane(links, device, cfg, self.keep) for _ in range(2)]
+        self.h_in = None
+        x0_dtype = None
+        if host is not None:
+            rows = cfg.chunks * cfg.chunk
+            if host.B < rows or host.J != cfg.J:
+                raise ValueError(f"the host batch needs {rows} rows of stride {cfg.J}")
+            x0 = host.x0[:rows]
+            if x0_f32:
+                x0 = x0.astype(np.float32)
+                if not np.array_equal(x0.astype(np.float64), host.x0[:rows]):
+                    raise ValueError("host positions are not exact in single precision")
+                x0_dtype = torch.float32
+            pin = lambda a: torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
+            self.h_in = {"n": pin(host.n[:rows].astype(np.uint8)), "adj": pin(host.adj[:rows].view(np.int32)),
+                         "fixed": pin(host.fixed[:rows].view(np.int32)), "motor": pin(host.motor[:rows].astype(np.uint8)),
+                         "x0": pin(x0)}
+        self.lanes = [_Lane(links, device, cfg, self.keep, x0_dtype) for _ in range(2)]
         if tuning:
             from . import tune
             for lane in self.lanes:
                 tune.apply(lane.ctx, tuning)
-        self.totals = {"candidates": 0, "valid": 0, "dropped": 0, "d2h_bytes": 0}
+        self.totals = {"candidates": 0, "valid": 0, "dropped": 0, "d2h_bytes": 0, "h2d_bytes": 0}
 
     def _compute(self, lane: _Lane, c: int):
         """Chunk c on the lane's stream, behind the copies of its previous chunk."""
@@ -175,9 +202,15 @@ class Streamer:
         cfg, L = self.cfg, self.L
         s = lane.stream
         with torch.cuda.stream(s):
-            lane.ctx.generate_dyads(cfg.chunk, cfg.seed, first=c * cfg.chunk, J=cfg.J, n_lo=cfg.n_lo,
-                                    n_hi=cfg.n_hi, paper_mode=cfg.paper_mode, rules=cfg.rules, out=lane.batch,
-                                    stream=s)
+            if self.h_in is not None:
+                lo, hi = c * cfg.chunk, (c + 1) * cfg.chunk
+                b = lane.batch
+                for name, dst in (("n", b.n), ("adj", b.adj), ("fixed", b.fixed), ("motor", b.motor), ("x0", b.x0)):
+                    dst.copy_(self.h_in[name][lo:hi], non_blocking=True)
+            else:
+                lane.ctx.generate_dyads(cfg.chunk, cfg.seed, first=c * cfg.chunk, J=cfg.J, n_lo=cfg.n_lo,
+                                        n_hi=cfg.n_hi, paper_mode=cfg.paper_mode, rules=cfg.rules, out=lane.batch,
+                                        stream=s)
             lane.ctx.simulate(lane.batch, T=cfg.T, precision=cfg.precision, write=L.WRITE_VALID, cap=cfg.cap,
                               out=lane.out, stream=s)
             lane.ctx.normalize_paths_n(lane.out["path"], lane.out["n_written"], cfg.norm, out=lane.norm,
@@ -221,6 +254,8 @@ class Streamer:
         t["valid"] += rec.k
         t["dropped"] += rec.k - kk
         t["d2h_bytes"] += kk * (cfg.T * 8 + 4 + 20)
+        if self.h_in is not None:
+            t["h2d_bytes"] += sum(v[:cfg.chunk].numel() * v.element_size() for v in self.h_in.values())
         if progress is not None:
             progress.save(cfg, c + 1, t)
 
@@ -234,7 +269,7 @@ class Streamer:
         cfg = self.cfg
         progress = Progress(progress_path) if progress_path else None
         start = 0
-        self.totals = {"candidates": 0, "valid": 0, "dropped": 0, "d2h_bytes": 0}
+        self.totals = {"candidates": 0, "valid": 0, "dropped": 0, "d2h_bytes": 0, "h2d_bytes": 0}
         if progress is not None:
             st = progress.load(cfg)
             if st is not None:

@@ -282,6 +282,27 @@ def test_wave_per_candidate_fp64_passes(ctx, L, name, B, seed, T, branch):
     assert np.array_equal(z["path"], ref["path"], equal_nan=True)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_wave_per_candidate_status_fixtures(ctx, L, precision):
+    """The wave-per-candidate FP64 passes on the fixtures (a drifting link, a
+    consistent redundant link, degenerate and locking mechanisms, no placed
+    joints): statuses, failure steps and paths equal to the oracle's."""
+    b = _fixtures()
+    prev = ctx.get_option("wave64")
+    try:
+        ctx.set_option("wave64", 7)
+        for T in (4, 8, 200):
+            r = _np(ctx.simulate(L.to_device(b), T=T, precision=precision, write=L.WRITE_ALL, path_dtype=L.F64))
+            ref = oracle.simulate(b, T=T, path=True)
+            assert np.array_equal(r["status"], ref["status"]), (T, r["status"], ref["status"])
+            assert np.array_equal(r["fail_step"], ref["fail_step"])
+            assert np.array_equal(np.isnan(r["path"]), np.isnan(ref["path"]))
+            tol = 1e-12 if precision == 1 else 1e-5 * _scale(b).max()
+            assert np.allclose(r["path"], ref["path"], rtol=0, atol=tol, equal_nan=True)
+    finally:
+        ctx.set_option("wave64", prev)
+
+
 def test_wave_per_candidate_falls_back_above_20_joints(ctx, L):
     """Above 20 joints the wave-per-candidate kernels do not apply and the other
     passes run: results equal with the option on or off."""

@@ -123,3 +123,30 @@ def test_stream_inspect_strided_statuses(L):
     assert np.array_equal(fs, r["fail_step"].cpu().numpy()[::7])
     with pytest.raises(ValueError):
         S.Streamer(cfg, keep_status=10, status_stride=0)
+
+
+@pytest.mark.parametrize("x0_f32", [False, True])
+def test_stream_from_host_batch(L, x0_f32):
+    """A stream fed from a batch in host memory (chunks copied from pinned memory
+    on each lane's stream) delivers the same chunks as the stream that generates
+    the same candidates on the device, with positions crossing in double or
+    (exact here) single precision."""
+    from paper_2208_14567_amd import gen
+    from paper_2208_14567_amd import stream as S
+    cfg = S.StreamConfig(seed=25, chunks=3, chunk=20000, cap=20000)
+    host = gen.dyad_batch(cfg.chunks * cfg.chunk, cfg.seed, gen.n_uniform(cfg.n_lo, cfg.n_hi), cfg.J)
+    dev, fed = Collect(), Collect()
+    S.Streamer(cfg).run(sink=dev)
+    tot = S.Streamer(cfg, host=host, x0_f32=x0_f32).run(sink=fed)
+    assert fed.order == [0, 1, 2]
+    for c in range(3):
+        assert _same(fed.got[c], dev.got[c]), c
+    per = cfg.chunk * (1 + 4 * cfg.J + 4 + 2 + cfg.J * 2 * (4 if x0_f32 else 8))
+    assert tot["h2d_bytes"] == 3 * per
+    with pytest.raises(ValueError):
+        S.Streamer(cfg, host=host.slice(0, 1000))
+    if x0_f32:
+        bad = host.slice(0, cfg.chunks * cfg.chunk)
+        bad.x0 = bad.x0 + 1e-9
+        with pytest.raises(ValueError):
+            S.Streamer(cfg, host=bad, x0_f32=True)
