@@ -247,7 +247,10 @@ def test_handover_queue_order(ctx, L):
 
 @pytest.mark.parametrize("name,B,seed,T,branch", [("dyad_6_20", 30000, 41, 200, 0), ("dyad_4_20", 20000, 42, 77, 0),
                                                   ("paper_8_20", 8000, 43, 200, 0), ("dyad_skewed", 20000, 44, 1500, 0),
-                                                  ("dyad_6_20", 20000, 45, 200, 1), ("fourbar_u", 5000, 46, 200, 0)])
+                                                  ("dyad_6_20", 20000, 45, 200, 1), ("fourbar_u", 5000, 46, 200, 0),
+                                                  ("dyad_4_20", 5000, 48, 1, 0), ("dyad_4_20", 5000, 49, 2, 0),
+                                                  ("dyad_4_20", 5000, 50, 63, 0), ("dyad_4_20", 5000, 51, 64, 0),
+                                                  ("dyad_4_20", 5000, 52, 127, 1)])
 def test_wave_per_candidate_fp64_passes(ctx, L, name, B, seed, T, branch):
     """The FP64 passes with one candidate per wave (positions in registers, 63
     steps per round) take every decision of the segmented and step-by-step passes:
