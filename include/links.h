@@ -172,7 +172,7 @@ typedef struct {
  * from the FP32 pass and the FP64 hand-over pass (or the FP64 pass alone); the
  * paths of the selected candidates are then recomputed by a path pass in FP64
  * (the correctly rounded sequence in FP64 precision, reciprocal square roots with
- * Newton steps otherwise) and written straight into their rows.  Per step t the tip is turned by
+ * a Newton step otherwise) and written straight into their rows.  Per step t the tip is turned by
  * theta_t about the pivot, fixed joints stay at x0, and every joint of the solve
  * order is placed at an intersection of the circles about its two parents (radii
  * = initial link lengths).  Of the two intersections the one nearer the joint's
@@ -256,7 +256,7 @@ int links_set_tuning(links_ctx* ctx, int waves32, int refill_min, int waves64);
  *   "refill64"        idle lanes a wave of the FP64 passes waits for before it
  *                     fetches new candidates (1..64, default 32);
  *   "exact_handover"  0 (default): the FP64 hand-over pass uses reciprocal square
- *                     roots refined by Newton steps (relative error ~1e-15); 1: the
+ *                     roots refined by a Newton step (relative error ~5e-15); 1: the
  *                     correctly rounded sequence of the FP64 precision (the
  *                     operations of an IEEE double evaluation, as in LINKS_FP64);
  *   "par64"           which FP64 passes run parallel in time: 16 lanes share one

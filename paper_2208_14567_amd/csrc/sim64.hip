@@ -16,7 +16,7 @@
 //   base  = p_a + (f/d)(dx, dy),  off = (h/d)(-dy, dx)
 //   p     = base + off or base - off, the one nearer the previous position (tie: +)
 // The fast variant evaluates the same intersection with reciprocal square roots
-// refined by two Newton steps and fused multiply-adds (relative error ~1e-15):
+// refined by one Newton step and fused multiply-adds (relative error ~5e-15):
 //   1/d = rsq(d^2), alpha = 1/2 + Kc/d^2, beta = sqrt(K)/(2 d^2), Kc = (ra^2-rb^2)/2,
 //   base = p_a + alpha (dx, dy), off = beta (-dy, dx), side by the sign of
 //   (prev - base) . off.
@@ -41,13 +41,13 @@ __device__ inline double sqd2(double ax, double ay, double bx, double by) {
   return dx * dx + dy * dy;
 }
 
-// 1/sqrt(x) for x > 0: hardware estimate and two Newton steps
+// 1/sqrt(x) for x > 0: hardware estimate (relative error below 2^-24 on gfx950)
+// and one Newton step (below 2^-47; 4.2e-15 measured over 4M inputs spanning 600
+// binades)
 __device__ __forceinline__ double rsqrt_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
+  const double y = __builtin_amdgcn_rsq(x);
   const double hx = 0.5 * x;
-  y = y * fma(-hx * y, y, 1.5);
-  y = y * fma(-hx * y, y, 1.5);
-  return y;
+  return y * fma(-hx * y, y, 1.5);
 }
 
 // Length drift of the links outside the solve order (only candidates with

@@ -77,12 +77,12 @@ __device__ __forceinline__ double lane_d(double v, int l) {
                           __builtin_amdgcn_readlane(__double2loint(v), l));
 }
 
+// the fast variant's 1/sqrt(x), as in the segmented passes: hardware estimate and
+// one Newton step
 __device__ __forceinline__ double rsqrt_w(double x) {
-  double y = __builtin_amdgcn_rsq(x);
+  const double y = __builtin_amdgcn_rsq(x);
   const double hx = 0.5 * x;
-  y = y * fma(-hx * y, y, 1.5);
-  y = y * fma(-hx * y, y, 1.5);
-  return y;
+  return y * fma(-hx * y, y, 1.5);
 }
 
 __device__ __forceinline__ double sqd_w(double ax, double ay, double bx, double by) {
