@@ -286,9 +286,9 @@ int links_set_tuning(links_ctx* ctx, int waves32, int refill_min, int waves64);
  *   "path_chunks"     1 (default): path rows are computed in chunks of 32 steps,
  *                     each on a lane of its own, from the sides of every placed
  *                     joint that the decision passes record at the chunk ends
- *                     (FP64 and FP32_RECHECK precision; not with "par32",
- *                     "drain32", "deesc" > 0, "par64" = 2 or the path pass of
- *                     "wave64"); 0: whole rows.  Rows are the same either way. */
+ *                     (FP64 and FP32_RECHECK precision; not with "deesc" > 0,
+ *                     "par64" = 2 or the path pass of "wave64"); 0: whole rows.
+ *                     Rows are the same either way. */
 int links_set_option(links_ctx* ctx, const char* name, int value);
 /* Current value of a named option in *value (LINKS_ERR_ARG for an unknown name). */
 int links_get_option(links_ctx* ctx, const char* name, int* value);

@@ -596,11 +596,10 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   const size_t nblocks = (size_t)prep_blocks(B);
   // Path rows in chunks of kPathChunk steps, each on a lane of its own, starting
   // from the sides the decision passes record at the chunk boundaries (the FP32
-  // pass for the steps it decides, the FP64 passes for theirs).  Rows are
-  // computed whole with the parallel-in-time FP32 pass, its drain hand-off, the
-  // return to FP32 after a hand-over, or par64 = 2; and without escalation
-  // (FP32_ONLY), whose FP32 sides near a tie need not be those the FP64 path
-  // pass takes.
+  // pass, step by step or parallel in time, for the steps it decides, the FP64
+  // passes for theirs).  Rows are computed whole with the return to FP32 after a
+  // hand-over or par64 = 2; and without escalation (FP32_ONLY), whose FP32 sides
+  // near a tie need not be those the FP64 path pass takes.
   const int ck_n = (T + kPathChunk - 1) / kPathChunk;
   // the FP64 passes a wave-per-candidate kernel runs (up to 20 joints; not with the
   // return to FP32 after a hand-over)
@@ -611,7 +610,7 @@ int simulate_impl(links_ctx* ctx, const links_batch* batch, const links_sim_opts
   const bool chunks = !wave_path && ctx->path_chunks && opts->write != LINKS_WRITE_NONE &&
                       !(opts->write == LINKS_WRITE_VALID && out->cap == 0) && ck_n > 1 && ctx->par64 != 2 &&
                       (opts->precision == LINKS_FP64 ||
-                       (opts->precision == LINKS_FP32_RECHECK && !ctx->par32 && ctx->deesc == 0 && ctx->drain32 == 0));
+                       (opts->precision == LINKS_FP32_RECHECK && ctx->deesc == 0));
   if (chunks && (rc = ensure_t(ctx, "side_ck", (size_t)B * ck_n, &side_ck))) return rc;
   // drain hand-off: the parallel-in-time pass's counters, its work queue and the
   // handed-on error bounds

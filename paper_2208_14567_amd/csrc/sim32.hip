@@ -848,6 +848,10 @@ __global__ void __launch_bounds__(256) simpar32_kernel(SimArgs A) {
     const int info = __shfl(ev | (ev_s << 8), seg0 + (f < kSeg32 ? f : 0));
     int kind = f < kSeg32 ? (info & 0xFF) : kE32None;
     int te = t0 - 1 + f;
+    // the sides of each decided step that ends a chunk of a path row (the lanes
+    // before the segment's first event), for the chunked path pass
+    if (A.side_ck != nullptr && comp && r > 0 && r < f && t + 1 < T && ((t + 1) & (kPathChunk - 1)) == 0)
+      A.side_ck[(size_t)cand * A.ck_n + (t + 1) / kPathChunk] = side;
     if (cand >= 0 && force64) {  // links outside the solve order: to FP64 at t = 0
       kind = kE32Band;
       te = 0;

@@ -38,7 +38,7 @@ SPACE: Dict[str, List[int]] = {
     "spread": [1, 0],
     "refill64": [8, 32],
     "deesc": [0, 8],
-    "drain32": [0, 16, 32],
+    "drain32": [0, 4, 12, 32],
     "sort_esc": [0, 1],
     "wave64": [0, 2],
 }

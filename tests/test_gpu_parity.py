@@ -324,11 +324,13 @@ def test_wave_per_candidate_falls_back_above_20_joints(ctx, L):
     assert np.array_equal(a["path"], z["path"], equal_nan=True)
 
 
-@pytest.mark.parametrize("precision", [0, 2])
-def test_parallel_in_time_fp32_pass(ctx, L, precision):
+@pytest.mark.parametrize("precision,T,branch", [(0, 200, 0), (2, 200, 0), (0, 77, 0), (0, 200, 1)])
+def test_parallel_in_time_fp32_pass(ctx, L, precision, T, branch):
     """The FP32 pass computed parallel in time takes every decision of the
-    step-by-step pass: statuses, failure and hand-over steps and paths equal."""
-    _say(f"[par32] precision={precision}")
+    step-by-step pass: statuses, failure and hand-over steps and paths equal (with
+    FP32 decisions and escalation the rows are computed in chunks from the sides
+    either pass records)."""
+    _say(f"[par32] precision={precision} T={T} branch={branch}")
     b = gen.workload("dyad_6_20", 30000, seed=22)
     db = L.to_device(b)
     res = {}
@@ -336,7 +338,8 @@ def test_parallel_in_time_fp32_pass(ctx, L, precision):
     try:
         for mode in (0, 1):
             ctx.set_option("par32", mode)
-            res[mode] = _np(ctx.simulate(db, T=200, precision=precision, write=L.WRITE_ALL, path_dtype=L.F64))
+            res[mode] = _np(ctx.simulate(db, T=T, precision=precision, branch=branch, write=L.WRITE_ALL,
+                                         path_dtype=L.F64))
     finally:
         ctx.set_option("par32", prev)
     a, z = res[0], res[1]

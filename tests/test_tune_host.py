@@ -3,7 +3,7 @@ from paper_2208_14567_amd.tune import SPACE, cache_key, coordinate_search
 
 
 def test_coordinate_search_finds_separable_minimum():
-    target = {"waves32": 4, "refill_min": 16, "chunk": 64, "spread": 0, "refill64": 8, "deesc": 8, "drain32": 16,
+    target = {"waves32": 4, "refill_min": 16, "chunk": 64, "spread": 0, "refill64": 8, "deesc": 8, "drain32": 12,
               "sort_esc": 1, "wave64": 2}
     calls = []
 
