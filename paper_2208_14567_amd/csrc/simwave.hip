@@ -28,9 +28,9 @@ constexpr int kWvStep = kWave - 1;
 // hand-over queue entries a wave claims with one atomic
 constexpr int kWvClaim = 4;
 
-// The positions of every slot at this lane's step.  A vector of registers is
-// allocated in sizes of 1, 2, 3, 4, 5, 8, 16 or 32 words, so more than 16 slots are
-// held as a 16-slot part and a 4-slot part (80 registers for 20 slots rather than
+// The positions of every slot at this lane's step.  A vector of registers above
+// 12 words is allocated as 16 or 32 words, so more than 16 slots are held as a
+// 16-slot part and a part for the rest (80 registers for 20 slots rather than
 // 128), the part chosen by a branch on the uniform index.
 template <int N>
 struct RegPart {
